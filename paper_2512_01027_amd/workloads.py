@@ -1,0 +1,191 @@
+"""Seeded synthetic inputs shaped like the paper's benchmark cases.
+
+This module holds initial fields and case parameters only -- none of the
+method's arithmetic -- so that the HIP path and the CPU reference can both be
+fed from it.  Arrays are float64, node layout (nz, ny, nx) with x fastest;
+velocity is (dim, nz, ny, nx).  Node i sits at coordinate i; a halfway wall
+lies half a node outside the first and last node.
+
+The interface profile is phi = 1/2 + 1/2 tanh(2 d / W), d the signed distance
+into the heavy fluid (phi = 1), which is the stationary profile of the
+conservative Allen-Cahn model (Sec. II) with interface width W.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+# Model constants used in every validation case of the paper (Sec. III):
+# M = 0.166, W = 4, lambda_b = 1/6.
+PAPER_M = 0.166
+LAMBDA_B = 1.0 / 6.0
+
+
+def base_case(dim: int, nx: int, ny: int, nz: int = 1, **kw) -> dict:
+    cfg = {
+        "dim": dim, "nx": nx, "ny": ny, "nz": nz if dim == 3 else 1,
+        "q_hydro": 9 if dim == 2 else 27, "q_phase": 9 if dim == 2 else 19,
+        "wall": (0, 0, 0), "delta_theta": 1,
+        "rho_heavy": 1000.0, "rho_light": 1.0,
+        "nu_heavy": 0.1, "nu_light": 0.1,
+        "sigma": 0.01, "W": 4.0, "M": PAPER_M, "lambda_bulk": LAMBDA_B,
+        "gravity": (0.0, 0.0, 0.0), "store": "fp64",
+    }
+    cfg.update(kw)
+    return cfg
+
+
+def _grid(cfg):
+    nz, ny, nx = cfg["nz"], cfg["ny"], cfg["nx"]
+    z, y, x = np.meshgrid(np.arange(nz, dtype=np.float64), np.arange(ny, dtype=np.float64),
+                          np.arange(nx, dtype=np.float64), indexing="ij")
+    return x, y, z
+
+
+def tanh_profile(d, W):
+    return 0.5 + 0.5 * np.tanh(2.0 * d / W)
+
+
+def _zero_fields(cfg):
+    shape = (cfg["nz"], cfg["ny"], cfg["nx"])
+    return np.zeros(shape), np.zeros((cfg["dim"],) + shape)
+
+
+def droplet(cfg, R, center=None, u0=None, P0=0.0, heavy_inside=True):
+    """A sphere (3D) or disc (2D) of radius R; heavy fluid inside unless
+    ``heavy_inside`` is False (a bubble)."""
+    x, y, z = _grid(cfg)
+    if center is None:
+        center = (cfg["nx"] / 2.0, cfg["ny"] / 2.0, cfg["nz"] / 2.0)
+    r2 = (x - center[0]) ** 2 + (y - center[1]) ** 2
+    if cfg["dim"] == 3:
+        r2 = r2 + (z - center[2]) ** 2
+    d = R - np.sqrt(r2)
+    phi = tanh_profile(d if heavy_inside else -d, cfg["W"])
+    P, u = _zero_fields(cfg)
+    P += P0
+    if u0 is not None:
+        for a in range(cfg["dim"]):
+            u[a] += u0[a]
+    return phi, P, u
+
+
+def slab(cfg, lo, hi, axis=0):
+    """Heavy layer between two flat interfaces at coordinates lo < hi."""
+    x, y, z = _grid(cfg)
+    s = (x, y, z)[axis]
+    d = np.minimum(s - lo, hi - s)
+    phi = tanh_profile(d, cfg["W"])
+    P, u = _zero_fields(cfg)
+    return phi, P, u
+
+
+def dam_block(cfg, bx, bz):
+    """Heavy block x < bx, z < bz (all y) in the corner of a walled box."""
+    x, y, z = _grid(cfg)
+    dx = (bx - 0.5) - x
+    dz = (bz - 0.5) - z
+    d = np.minimum(dx, dz)
+    corner = (dx < 0) & (dz < 0)
+    d = np.where(corner, -np.sqrt(dx * dx + dz * dz), d)
+    phi = tanh_profile(d, cfg["W"])
+    P, u = _zero_fields(cfg)
+    return phi, P, u
+
+
+def add_noise(phi, amp, seed):
+    """phi + U(-amp, amp) from NumPy PCG64(seed), clipped to [0, 1]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.clip(phi + rng.uniform(-amp, amp, size=phi.shape), 0.0, 1.0)
+
+
+def random_smooth(cfg, seed, amp=0.05, modes=3):
+    """Random smooth periodic perturbations (sum of low Fourier modes)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x, y, z = _grid(cfg)
+    out = np.zeros(x.shape)
+    for _ in range(modes):
+        kx, ky = rng.integers(1, 3, size=2)
+        kz = rng.integers(1, 3) if cfg["dim"] == 3 else 0
+        ph = rng.uniform(0, 2 * math.pi)
+        a = rng.uniform(-amp, amp)
+        out += a * np.sin(2 * math.pi * (kx * x / cfg["nx"] + ky * y / cfg["ny"] +
+                                         kz * z / cfg["nz"]) + ph)
+    return out
+
+
+def shear_wave(cfg, amp=1e-4, heavy=False):
+    """Single-phase u_x = amp sin(2 pi y / ny)."""
+    x, y, z = _grid(cfg)
+    phi = np.full(x.shape, 1.0 if heavy else 0.0)
+    P, u = _zero_fields(cfg)
+    u[0] = amp * np.sin(2 * math.pi * y / cfg["ny"])
+    return phi, P, u
+
+
+# ----------------------------------------------------------------- named cases
+
+def config_static_droplet_2d():
+    """2D 64x64 periodic static droplet R = 16 (rho ratio 1000, sigma 0.01,
+    nu 0.1 both, W 4), D2Q9 / D2Q9, FP64."""
+    cfg = base_case(2, 64, 64, sigma=0.01, nu_heavy=0.1, nu_light=0.1, W=4.0, store="fp64")
+    phi, P, u = droplet(cfg, 16.0, center=(32.0, 32.0, 0.0))
+    return cfg, (phi, P, u), 2000
+
+
+def config_galilean_droplet_3d(n=128):
+    """3D n^3 periodic droplet R = 24 translated with u = (0.05, 0.02, 0);
+    D3Q27 hydro + D3Q19 phase field, FP32 store / FP32 compute."""
+    cfg = base_case(3, n, n, n, sigma=0.005, nu_heavy=0.05, nu_light=0.05, W=4.0, store="fp32")
+    R = 24.0 * n / 128.0
+    phi, P, u = droplet(cfg, R, center=(n / 2, n / 2, n / 2), u0=(0.05, 0.02, 0.0))
+    return cfg, (phi, P, u), 5000
+
+
+def config_rising_bubble_3d(n=256, store="fp32", seed=1):
+    """3D n^3 with walls in z and gravity -1e-6 z: air bubble R = 32 at a
+    quarter height in water; phi + U(-1e-3, 1e-3) (seed 1)."""
+    cfg = base_case(3, n, n, n, wall=(0, 0, 1), gravity=(0.0, 0.0, -1e-6), sigma=0.01,
+                    nu_heavy=0.02, nu_light=0.2, W=5.0, store=store)
+    R = 32.0 * n / 256.0
+    phi, P, u = droplet(cfg, R, center=(n / 2, n / 2, n / 4), heavy_inside=False)
+    phi = add_noise(phi, 1e-3, seed)
+    return cfg, (phi, P, u), 4000
+
+
+def config_dam_break_3d(nx=512, ny=256, nz=256, store="fp16"):
+    """3D nx x ny x nz, walls on all faces, gravity -2e-6 z: water block
+    (nx/4) x ny x (nz/2) in the corner."""
+    cfg = base_case(3, nx, ny, nz, wall=(1, 1, 1), gravity=(0.0, 0.0, -2e-6), sigma=0.005,
+                    nu_heavy=0.01, nu_light=0.15, W=4.0, store=store)
+    phi, P, u = dam_block(cfg, nx // 4, nz // 2)
+    return cfg, (phi, P, u), 20000
+
+
+def serving_case(rng, store="fp16"):
+    """One request of the serving stream: 75% 3D (n log-uniform in [32, 192]),
+    25% 2D (n log-uniform in [128, 1024]); static droplet or rising bubble;
+    density ratio in {10, 100, 1000}; R = n/6; 1000..10000 steps."""
+    is3d = rng.uniform() < 0.75
+    if is3d:
+        n = int(round(math.exp(rng.uniform(math.log(32), math.log(192)))))
+    else:
+        n = int(round(math.exp(rng.uniform(math.log(128), math.log(1024)))))
+    kind = "droplet" if rng.uniform() < 0.5 else "bubble"
+    ratio = float(rng.choice([10.0, 100.0, 1000.0]))
+    steps = int(rng.integers(1000, 10001))
+    dim = 3 if is3d else 2
+    R = n / 6.0
+    if kind == "droplet":
+        cfg = base_case(dim, n, n, n, rho_heavy=ratio, rho_light=1.0, sigma=0.005 if is3d else 0.01,
+                        nu_heavy=0.05, nu_light=0.05, W=4.0, store=store)
+        phi, P, u = droplet(cfg, R)
+    else:
+        g = (0.0, -1e-6, 0.0) if dim == 2 else (0.0, 0.0, -1e-6)
+        wall = (0, 1, 0) if dim == 2 else (0, 0, 1)
+        cfg = base_case(dim, n, n, n, rho_heavy=ratio, rho_light=1.0, sigma=0.01, nu_heavy=0.02,
+                        nu_light=0.2, W=5.0, wall=wall, gravity=g, store=store)
+        c = (n / 2, n / 4, 0.0) if dim == 2 else (n / 2, n / 2, n / 4)
+        phi, P, u = droplet(cfg, R, center=c, heavy_inside=False)
+    return cfg, (phi, P, u), steps, kind
