@@ -1,0 +1,152 @@
+/*
+ * pulbm.h -- C ABI of libpulbm.so, the MI355X (gfx950) HIP solver for the
+ * coupled phase-field + P-u lattice Boltzmann step of Otomo et al.,
+ * "Lattice Boltzmann models for the hydrodynamic equations in multiphase flow
+ * with high density ratio" (arXiv 2512.01027).
+ *
+ * The calls follow the paper's statement of the problem (Sec. II): fluid
+ * properties (rho, nu of both fluids, sigma, W, M, lambda_b, body force) and
+ * geometry go in, the initial phi, P, u are turned into equilibrium
+ * distributions (Sec. I, the initial state is the equilibrium), the coupled
+ * step is advanced N times, and phi, P, u are read back (the zeroth moment of
+ * h and the P/u reconstruction of Sec. II).
+ *
+ * General rules
+ *  - Every call returns 0 (PULBM_OK) or a negative PULBM_E* code and never
+ *    throws; pulbm_last_error() then describes the failure (thread-local).
+ *  - Host arrays are caller-owned, FP64, node index n = x + nx*(y + ny*z)
+ *    (x fastest; 2D uses nz = 1), vector fields SoA: u[a*N + n].  They are
+ *    copied; the library keeps no host pointer.
+ *  - Device memory is either allocated by the library (hipMalloc) or carved
+ *    from a caller-owned device arena (e.g. a torch tensor) that must outlive
+ *    the case and be at least pulbm_required_bytes() long.
+ *  - All work on a case is ordered on the HIP stream given at creation (NULL
+ *    = the default stream).  pulbm_step() returns as soon as the launches are
+ *    queued; read, diagnostics and checkpoint calls synchronise the stream.
+ *  - One MI355X per process; a case lives on the device that was current at
+ *    pulbm_create().
+ */
+#ifndef PULBM_H
+#define PULBM_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PULBM_OK 0
+#define PULBM_EINVAL (-1)    /* bad argument or parameter                         */
+#define PULBM_ENOMEM (-2)    /* device allocation failed / arena too small        */
+#define PULBM_EDEVICE (-3)   /* a HIP call failed                                 */
+#define PULBM_EDIVERGED (-4) /* non-finite values found in the fields             */
+#define PULBM_ESTATE (-5)    /* call out of order (e.g. step before init)         */
+#define PULBM_EAGAIN (-6)    /* serving: no free slot or memory for the request   */
+
+/* Storage precision of the distributions (compute precision in brackets). */
+#define PULBM_STORE_FP64 0 /* FP64 (FP64)                                             */
+#define PULBM_STORE_FP32 1 /* FP32 (FP32; pressure reconstruction and sums in FP64)   */
+#define PULBM_STORE_FP16 2 /* FP16 shifted and scaled populations (FP32 compute)      */
+#define PULBM_STORE_BF16 3 /* BF16 shifted populations (FP32 compute)                 */
+
+/* Case parameters, lattice units (Sec. II; defaults of Sec. III in brackets). */
+typedef struct {
+    int32_t dim, nx, ny, nz;     /* dim 2 (nz = 1) or 3; every n >= 1                      */
+    int32_t q_hydro, q_phase;    /* 2D: 9, 9; 3D: 27, 19 (hydro D3Q27, phase field D3Q19)   */
+    int32_t wall[3];             /* per axis: 0 periodic, 1 no-slip walls at both ends      */
+    int32_t delta_theta;         /* 1: apply the delta-theta correction of Sec. II [1]      */
+    int32_t store;               /* PULBM_STORE_*                                           */
+    int32_t reserved;            /* must be 0                                               */
+    double rho_heavy, rho_light; /* densities of the phi = 1 and phi = 0 fluids              */
+    double nu_heavy, nu_light;   /* kinematic viscosities (> 0)                             */
+    double sigma, W, M;          /* surface tension, interface width, mobility [M = 0.166]  */
+    double lambda_bulk;          /* bulk viscosity [1/6]                                    */
+    double gravity[3];           /* body force per unit mass, F_ext = rho g                 */
+    double phi_ref;              /* FP16/BF16: h is stored as h_j - w_j phi_ref; a negative
+                                    value lets init_fields pick 0 or 1 from the mean of phi0 */
+} pulbm_params;
+
+typedef struct {
+    double phi_sum;     /* sum of phi over the nodes (FP64)              */
+    double u_sum[3];    /* sum of u                                      */
+    double rhou_sum[3]; /* sum of rho u                                  */
+    double umax;        /* max |u|                                       */
+    int64_t nonfinite;  /* nodes with a non-finite phi, P or u component */
+    int64_t step;       /* steps taken since init                        */
+} pulbm_diag;
+
+typedef struct pulbm_case pulbm_case;
+
+/* Device bytes a case needs (for a caller-provided arena). */
+int pulbm_required_bytes(const pulbm_params* p, size_t* bytes);
+
+/* Validate p and create a case.  dev_arena may be NULL (library allocates);
+ * hip_stream may be NULL (default stream).  *out receives the handle. */
+int pulbm_create(const pulbm_params* p, void* dev_arena, size_t arena_bytes, void* hip_stream,
+                 pulbm_case** out);
+
+/* Equilibrium initialisation from host phi[N], P[N], u[dim*N] (Sec. I: the
+ * distributions start at equilibrium; the previous-step pressure is P). */
+int pulbm_init_fields(pulbm_case* c, const double* phi, const double* P, const double* u);
+
+/* Queue nsteps coupled steps (moments, pressure, collide+stream) on the
+ * case's stream.  Returns without waiting. */
+int pulbm_step(pulbm_case* c, int64_t nsteps);
+
+/* Like pulbm_step, but waits and adds the GPU time of each of the three
+ * kernels (moments, pressure, collide) to ms[0..2] (HIP events on the case's
+ * stream around every launch). */
+int pulbm_step_timed(pulbm_case* c, int64_t nsteps, double* ms);
+
+/* phi[N], P[N], u[dim*N] of the current state: the moment stage applied to
+ * the current distributions without changing them.  Synchronises. */
+int pulbm_read_fields(pulbm_case* c, double* phi, double* P, double* u);
+
+/* Conservation diagnostics of the current state (FP64 wave reductions).
+ * Returns PULBM_EDIVERGED (with *d filled) if any value is non-finite. */
+int pulbm_diagnostics(pulbm_case* c, pulbm_diag* d);
+
+/* Restart image (distributions in their storage precision, previous-step
+ * pressure, step count, parameters).  checkpoint_bytes gives the size. */
+int pulbm_checkpoint_bytes(const pulbm_case* c, size_t* bytes);
+int pulbm_checkpoint(pulbm_case* c, void* host_buf, size_t bytes);
+int pulbm_restore(pulbm_case* c, const void* host_buf, size_t bytes);
+
+/* Wait for all queued work of the case. */
+int pulbm_sync(pulbm_case* c);
+int64_t pulbm_steps_done(const pulbm_case* c);
+void pulbm_destroy(pulbm_case* c);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* pulbm_last_error(void);
+
+/* ------------------------------------------------------------------ serving
+ * A batch keeps many cases resident in one device memory budget and advances
+ * all active cases together: each launch covers the tiles of every resident
+ * case of a lattice (2D or 3D), and a k-step advance is one replay of a
+ * captured HIP graph.  Each case runs exactly its requested number of steps;
+ * its arithmetic is the same as a single case's, so results do not depend on
+ * which other cases share the batch.  A batch uses one storage precision. */
+typedef struct pulbm_batch pulbm_batch;
+
+int pulbm_batch_create(size_t hbm_budget, int32_t store, int32_t max_slots, void* hip_stream,
+                       pulbm_batch** out);
+/* Admit a case (host FP64 initial fields) for nsteps steps.  Returns
+ * PULBM_EAGAIN if no slot or not enough of the budget is free; *slot gets the
+ * slot id otherwise.  p->store must equal the batch's store. */
+int pulbm_batch_admit(pulbm_batch* b, const pulbm_params* p, const double* phi, const double* P,
+                      const double* u, int64_t nsteps, int32_t* slot);
+/* Queue ksteps steps of every active case (a captured graph per ksteps). */
+int pulbm_batch_advance(pulbm_batch* b, int32_t ksteps);
+/* Slots whose cases have finished (synchronises); fills up to cap ids. */
+int pulbm_batch_poll(pulbm_batch* b, int32_t* done_slots, int32_t cap, int32_t* ndone);
+/* Read a finished case's phi, P, u (as pulbm_read_fields) and free its slot. */
+int pulbm_batch_take(pulbm_batch* b, int32_t slot, double* phi, double* P, double* u);
+/* Bytes of the budget in use, number of active cases. */
+int pulbm_batch_usage(const pulbm_batch* b, size_t* used, int32_t* active);
+void pulbm_batch_destroy(pulbm_batch* b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

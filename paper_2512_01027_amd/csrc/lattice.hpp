@@ -1,0 +1,75 @@
+// Velocity sets of the solver, as compile-time tables (every loop over
+// directions is fully unrolled, so c and w become immediates).
+//
+// Direction order: 0 is the rest direction; i and i+1 (i odd) are opposite.
+// The 3D phase-field set D3Q19 is the first 19 directions of D3Q27 (rest,
+// 6 faces, 12 edges) with its own weights.  Lattice temperature T = 1/3
+// (Sec. II of the paper).
+#pragma once
+
+namespace pulbm {
+
+constexpr double kT = 1.0 / 3.0;
+
+__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+
+struct D2Q9 {
+    static constexpr int Q = 9;
+    static constexpr int DIM = 2;
+    __host__ __device__ static constexpr int c(int i, int a)
+    {
+        constexpr int t[9][3] = {{0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0},
+                                 {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}};
+        return t[i][a];
+    }
+    __host__ __device__ static constexpr double w(int i)
+    {
+        return i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+    }
+};
+
+struct D3Q27 {
+    static constexpr int Q = 27;
+    static constexpr int DIM = 3;
+    __host__ __device__ static constexpr int c(int i, int a)
+    {
+        constexpr int t[27][3] = {
+            {0, 0, 0},   {1, 0, 0},    {-1, 0, 0},   {0, 1, 0},   {0, -1, 0},  {0, 0, 1},
+            {0, 0, -1},  {1, 1, 0},    {-1, -1, 0},  {1, -1, 0},  {-1, 1, 0},  {1, 0, 1},
+            {-1, 0, -1}, {1, 0, -1},   {-1, 0, 1},   {0, 1, 1},   {0, -1, -1}, {0, 1, -1},
+            {0, -1, 1},  {1, 1, 1},    {-1, -1, -1}, {1, 1, -1},  {-1, -1, 1}, {1, -1, 1},
+            {-1, 1, -1}, {1, -1, -1},  {-1, 1, 1}};
+        return t[i][a];
+    }
+    __host__ __device__ static constexpr double w(int i)
+    {
+        return i == 0 ? 8.0 / 27.0 : (i < 7 ? 2.0 / 27.0 : (i < 19 ? 1.0 / 54.0 : 1.0 / 216.0));
+    }
+};
+
+struct D3Q19 {
+    static constexpr int Q = 19;
+    static constexpr int DIM = 3;
+    __host__ __device__ static constexpr int c(int i, int a) { return D3Q27::c(i, a); }
+    __host__ __device__ static constexpr double w(int i)
+    {
+        return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+    }
+};
+
+// Hydro lattice G, phase-field lattice H and the workgroup tile of a
+// problem dimension.  Tiles are 256 threads (four 64-wide wavefronts), x
+// fastest so that a wavefront reads whole 128-byte rows of a population.
+template <int DIMV> struct Model;
+template <> struct Model<2> {
+    using G = D2Q9;
+    using H = D2Q9;
+    static constexpr int TX = 64, TY = 4, TZ = 1;
+};
+template <> struct Model<3> {
+    using G = D3Q27;
+    using H = D3Q19;
+    static constexpr int TX = 32, TY = 4, TZ = 2;
+};
+
+}  // namespace pulbm

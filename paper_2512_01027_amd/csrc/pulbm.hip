@@ -1,0 +1,780 @@
+// libpulbm.so: C ABI (include/pulbm.h) around the HIP kernels of kernels.hpp.
+//
+// Host-side responsibilities: parameter validation, device memory layout of a
+// case (library- or caller-owned), kernel dispatch per lattice / storage
+// precision, read-back, diagnostics, restart images and the serving batch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "pulbm.h"
+
+using namespace pulbm;
+
+// ------------------------------------------------------------------ errors
+
+static thread_local std::string g_err;
+
+static int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+static int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPC(expr)                                                                           \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(PULBM_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));       \
+    } while (0)
+
+extern "C" const char* pulbm_last_error(void) { return g_err.c_str(); }
+
+// ------------------------------------------------------------ case layout
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+int store_bytes(int store) { return store == PULBM_STORE_FP64 ? 8 : store == PULBM_STORE_FP32 ? 4 : 2; }
+int aux_bytes(int store) { return store == PULBM_STORE_FP64 ? 8 : 4; }
+
+struct Layout {
+    size_t h, g, P0, P1, phi, J, S, M2, U, desc, tab, partial, diag, total;
+};
+
+Layout make_layout(const pulbm_params& p)
+{
+    const size_t N = (size_t)p.nx * p.ny * p.nz;
+    const size_t sb = store_bytes(p.store), ab = aux_bytes(p.store);
+    const int dim = p.dim, nm = dim == 2 ? 3 : 6;
+    Layout L;
+    size_t o = 0;
+    auto put = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
+    L.h = put((size_t)p.q_phase * N * sb);
+    L.g = put((size_t)p.q_hydro * N * sb);
+    L.P0 = put(N * ab);
+    L.P1 = put(N * ab);
+    L.phi = put(N * ab);
+    L.J = put((size_t)dim * N * ab);
+    L.S = put(N * ab);
+    L.M2 = put((size_t)nm * N * ab);
+    L.U = put((size_t)dim * N * ab);
+    L.desc = put(sizeof(CaseDev));
+    L.tab = put(sizeof(CaseDev*) + 2 * sizeof(int));
+    L.partial = put((size_t)kDiagBlocks * kDiagVals * sizeof(double));
+    L.diag = put(kDiagVals * sizeof(double));
+    L.total = o;
+    return L;
+}
+
+int validate(const pulbm_params* p)
+{
+    if (!p) return fail(PULBM_EINVAL, "params is NULL");
+    if (p->dim != 2 && p->dim != 3) return fail(PULBM_EINVAL, "dim must be 2 or 3 (got %d)", p->dim);
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(PULBM_EINVAL, "grid sizes must be >= 1");
+    if (p->dim == 2 && p->nz != 1) return fail(PULBM_EINVAL, "2D cases need nz = 1");
+    if (p->dim == 2 && (p->q_hydro != 9 || p->q_phase != 9))
+        return fail(PULBM_EINVAL, "2D cases use D2Q9 for both lattices (q_hydro = q_phase = 9)");
+    if (p->dim == 3 && (p->q_hydro != 27 || p->q_phase != 19))
+        return fail(PULBM_EINVAL, "3D cases use D3Q27 hydro + D3Q19 phase field (27, 19)");
+    if ((double)p->nx * p->ny * p->nz > 2.0e9) return fail(PULBM_EINVAL, "grid too large");
+    if (p->store < PULBM_STORE_FP64 || p->store > PULBM_STORE_BF16) return fail(PULBM_EINVAL, "bad store %d", p->store);
+    if (p->reserved != 0) return fail(PULBM_EINVAL, "reserved field must be 0");
+    for (int a = 0; a < 3; ++a)
+        if (p->wall[a] != 0 && p->wall[a] != 1) return fail(PULBM_EINVAL, "wall[%d] must be 0 or 1", a);
+    if (p->dim == 2 && p->wall[2]) return fail(PULBM_EINVAL, "2D cases have no z walls");
+    if (!(p->rho_heavy > 0) || !(p->rho_light > 0) || !(p->rho_heavy > p->rho_light))
+        return fail(PULBM_EINVAL, "densities must satisfy rho_heavy > rho_light > 0");
+    if (!(p->nu_heavy > 0) || !(p->nu_light > 0)) return fail(PULBM_EINVAL, "viscosities must be > 0");
+    if (!(p->W > 0) || !(p->M > 0) || !(p->sigma >= 0) || !(p->lambda_bulk >= 0))
+        return fail(PULBM_EINVAL, "W, M must be > 0 and sigma, lambda_bulk >= 0");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(p->gravity[a])) return fail(PULBM_EINVAL, "gravity must be finite");
+    if (p->delta_theta != 0 && p->delta_theta != 1) return fail(PULBM_EINVAL, "delta_theta must be 0 or 1");
+    return PULBM_OK;
+}
+
+template <int DIMV> void tiles_of(const pulbm_params& p, int* ntx, int* nty, int* ntz)
+{
+    using Mo = Model<DIMV>;
+    *ntx = (p.nx + Mo::TX - 1) / Mo::TX;
+    *nty = (p.ny + Mo::TY - 1) / Mo::TY;
+    *ntz = (p.nz + Mo::TZ - 1) / Mo::TZ;
+}
+
+int grid_of(int tiles) { return ((tiles + 7) / 8) * 8; }
+
+}  // namespace
+
+struct pulbm_case {
+    pulbm_params p;
+    hipStream_t stream = nullptr;
+    char* base = nullptr;
+    bool own = false;
+    Layout L;
+    CaseDev h;          // host copy of the descriptor
+    CaseDev* d = nullptr;
+    CaseDev** tab = nullptr;  // device {d}
+    int* tstart = nullptr;    // device {0, ntiles}
+    int ntiles = 0;
+    int64_t step = 0;
+    bool ready = false;
+};
+
+// ------------------------------------------------------------ dispatch
+
+namespace {
+
+template <int DIMV, class S>
+void launch_step(hipStream_t st, CaseDev* const* tab, const int* tstart, int ncases, int tiles, int off,
+                 int which)
+{
+    using CT = typename Codec<S>::CT;
+    const dim3 grid(grid_of(tiles)), block(256);
+    if (which == 0) hipLaunchKernelGGL((k_moments<DIMV, S>), grid, block, 0, st, tab, tstart, ncases, tiles, off);
+    if (which == 1) hipLaunchKernelGGL((k_pressure<DIMV, CT>), grid, block, 0, st, tab, tstart, ncases, tiles, off);
+    if (which == 2) hipLaunchKernelGGL((k_collide<DIMV, S, false>), grid, block, 0, st, tab, tstart, ncases, tiles, off);
+    if (which == 3) hipLaunchKernelGGL((k_collide<DIMV, S, true>), grid, block, 0, st, tab, tstart, ncases, tiles, off);
+}
+
+template <int DIMV>
+void launch_dim(int store, hipStream_t st, CaseDev* const* tab, const int* tstart, int ncases, int tiles,
+                int off, int which)
+{
+    switch (store) {
+        case PULBM_STORE_FP64: launch_step<DIMV, double>(st, tab, tstart, ncases, tiles, off, which); break;
+        case PULBM_STORE_FP32: launch_step<DIMV, float>(st, tab, tstart, ncases, tiles, off, which); break;
+        case PULBM_STORE_FP16: launch_step<DIMV, _Float16>(st, tab, tstart, ncases, tiles, off, which); break;
+        default: launch_step<DIMV, bf16_t>(st, tab, tstart, ncases, tiles, off, which); break;
+    }
+}
+
+// which: 0 moments, 1 pressure, 2 collide, 3 read-pass velocity
+void launch(int dim, int store, hipStream_t st, CaseDev* const* tab, const int* tstart, int ncases, int tiles,
+            int off, int which)
+{
+    if (dim == 2) launch_dim<2>(store, st, tab, tstart, ncases, tiles, off, which);
+    else launch_dim<3>(store, st, tab, tstart, ncases, tiles, off, which);
+}
+
+template <int DIMV, class S>
+void launch_init_t(hipStream_t st, CaseDev* const* tab, const int* tstart, int tiles, const double* phi,
+                   const double* P, const double* u)
+{
+    hipLaunchKernelGGL((k_init<DIMV, S>), dim3(grid_of(tiles)), dim3(256), 0, st, tab, tstart, 1, tiles, phi, P, u);
+}
+
+void launch_init(int dim, int store, hipStream_t st, CaseDev* const* tab, const int* tstart, int tiles,
+                 const double* phi, const double* P, const double* u)
+{
+#define PULBM_INIT_CASE(D)                                                                          \
+    switch (store) {                                                                                \
+        case PULBM_STORE_FP64: launch_init_t<D, double>(st, tab, tstart, tiles, phi, P, u); break;  \
+        case PULBM_STORE_FP32: launch_init_t<D, float>(st, tab, tstart, tiles, phi, P, u); break;   \
+        case PULBM_STORE_FP16: launch_init_t<D, _Float16>(st, tab, tstart, tiles, phi, P, u); break;\
+        default: launch_init_t<D, bf16_t>(st, tab, tstart, tiles, phi, P, u); break;                \
+    }
+    if (dim == 2) { PULBM_INIT_CASE(2) } else { PULBM_INIT_CASE(3) }
+#undef PULBM_INIT_CASE
+}
+
+// Codec constants: FP16 stores (h - w phi_ref) * 2^12 and g * 2^12; BF16 keeps
+// the FP32 exponent range (scale 1) with the same shift.
+void codec_constants(const pulbm_params& p, double phi_ref, CaseDev& h)
+{
+    h.phi_ref = 0.0;
+    h.h_scale = h.h_inv_scale = h.g_scale = h.g_inv_scale = 1.0;
+    if (p.store == PULBM_STORE_FP16 || p.store == PULBM_STORE_BF16) {
+        h.phi_ref = phi_ref;
+        const double s = p.store == PULBM_STORE_FP16 ? 4096.0 : 1.0;
+        h.h_scale = h.g_scale = s;
+        h.h_inv_scale = h.g_inv_scale = 1.0 / s;
+    }
+}
+
+int upload_desc(pulbm_case* c)
+{
+    HIPC(hipMemcpyAsync(c->d, &c->h, sizeof(CaseDev), hipMemcpyHostToDevice, c->stream));
+    return PULBM_OK;
+}
+
+int read_pass(pulbm_case* c)
+{
+    for (int w = 0; w < 2; ++w) launch(c->p.dim, c->p.store, c->stream, c->tab, c->tstart, 1, c->ntiles, 0, w);
+    launch(c->p.dim, c->p.store, c->stream, c->tab, c->tstart, 1, c->ntiles, 0, 3);
+    HIPC(hipGetLastError());
+    return PULBM_OK;
+}
+
+template <class AT>
+void to_double(const std::vector<char>& raw, double* out, size_t n)
+{
+    const AT* src = (const AT*)raw.data();
+    for (size_t i = 0; i < n; ++i) out[i] = (double)src[i];
+}
+
+int fetch(pulbm_case* c, const void* dev, double* out, size_t n)
+{
+    if (!out) return PULBM_OK;
+    const size_t ab = aux_bytes(c->p.store);
+    std::vector<char> raw(n * ab);
+    HIPC(hipMemcpyAsync(raw.data(), dev, n * ab, hipMemcpyDeviceToHost, c->stream));
+    HIPC(hipStreamSynchronize(c->stream));
+    if (ab == 8) to_double<double>(raw, out, n);
+    else to_double<float>(raw, out, n);
+    return PULBM_OK;
+}
+
+}  // namespace
+
+// ================================================================ case API
+
+extern "C" int pulbm_required_bytes(const pulbm_params* p, size_t* bytes)
+{
+    int rc = validate(p);
+    if (rc) return rc;
+    if (!bytes) return fail(PULBM_EINVAL, "bytes is NULL");
+    *bytes = make_layout(*p).total;
+    return PULBM_OK;
+}
+
+extern "C" int pulbm_create(const pulbm_params* p, void* dev_arena, size_t arena_bytes, void* hip_stream,
+                            pulbm_case** out)
+{
+    if (!out) return fail(PULBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate(p);
+    if (rc) return rc;
+    pulbm_case* c = new (std::nothrow) pulbm_case();
+    if (!c) return fail(PULBM_ENOMEM, "host allocation failed");
+    c->p = *p;
+    c->stream = (hipStream_t)hip_stream;
+    c->L = make_layout(*p);
+    if (dev_arena) {
+        if (arena_bytes < c->L.total) {
+            delete c;
+            return fail(PULBM_ENOMEM, "arena of %zu bytes is smaller than the %zu required", arena_bytes,
+                        c->L.total);
+        }
+        if (((uintptr_t)dev_arena) % kAlign) {
+            delete c;
+            return fail(PULBM_EINVAL, "arena must be 256-byte aligned");
+        }
+        c->base = (char*)dev_arena;
+    } else {
+        hipError_t e = hipMalloc((void**)&c->base, c->L.total);
+        if (e != hipSuccess) {
+            delete c;
+            return fail(PULBM_ENOMEM, "hipMalloc(%zu) failed: %s", c->L.total, hipGetErrorString(e));
+        }
+        c->own = true;
+    }
+    const Layout& L = c->L;
+    CaseDev& h = c->h;
+    std::memset(&h, 0, sizeof h);
+    h.nx = p->nx; h.ny = p->ny; h.nz = p->nz; h.dim = p->dim;
+    for (int a = 0; a < 3; ++a) { h.wall[a] = p->wall[a]; h.grav[a] = p->gravity[a]; }
+    if (p->dim == 2) tiles_of<2>(*p, &h.ntx, &h.nty, &h.ntz);
+    else tiles_of<3>(*p, &h.ntx, &h.nty, &h.ntz);
+    c->ntiles = h.ntx * h.nty * h.ntz;
+    h.delta_theta = p->delta_theta;
+    h.N = (int64_t)p->nx * p->ny * p->nz;
+    h.step = 0;
+    h.step_end = INT64_MAX;
+    h.h = c->base + L.h; h.g = c->base + L.g;
+    h.P[0] = c->base + L.P0; h.P[1] = c->base + L.P1;
+    h.phi = c->base + L.phi; h.J = c->base + L.J; h.S = c->base + L.S;
+    h.M2 = c->base + L.M2; h.U = c->base + L.U;
+    h.rho_a = p->rho_light; h.rho_w = p->rho_heavy;
+    h.tau_a = p->nu_light / kT + 0.5;
+    h.tau_w = p->nu_heavy / kT + 0.5;
+    h.tau_phi = p->M / kT + 0.5;
+    h.M = p->M; h.W = p->W; h.sigma = p->sigma; h.lambda_b = p->lambda_bulk;
+    codec_constants(*p, p->phi_ref >= 0 ? p->phi_ref : 0.0, h);
+    c->d = (CaseDev*)(c->base + L.desc);
+    c->tab = (CaseDev**)(c->base + L.tab);
+    c->tstart = (int*)(c->base + L.tab + sizeof(CaseDev*));
+    struct { CaseDev* d; int ts[2]; } tabh = {c->d, {0, c->ntiles}};
+    hipError_t e = hipMemcpyAsync(c->tab, &tabh, sizeof(CaseDev*) + 2 * sizeof(int), hipMemcpyHostToDevice,
+                                  c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->d, &c->h, sizeof(CaseDev), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        pulbm_destroy(c);
+        return fail(PULBM_EDEVICE, "descriptor upload failed: %s", hipGetErrorString(e));
+    }
+    *out = c;
+    return PULBM_OK;
+}
+
+extern "C" void pulbm_destroy(pulbm_case* c)
+{
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    if (c->own && c->base) (void)hipFree(c->base);
+    delete c;
+}
+
+extern "C" int pulbm_init_fields(pulbm_case* c, const double* phi, const double* P, const double* u)
+{
+    if (!c || !phi || !P || !u) return fail(PULBM_EINVAL, "NULL argument");
+    const size_t N = (size_t)c->h.N;
+    const int dim = c->p.dim;
+    double mean = 0.0;
+    for (size_t n = 0; n < N; ++n) {
+        if (!std::isfinite(phi[n]) || !std::isfinite(P[n]))
+            return fail(PULBM_EDIVERGED, "non-finite initial phi or P at node %zu", n);
+        mean += phi[n];
+    }
+    for (size_t n = 0; n < (size_t)dim * N; ++n)
+        if (!std::isfinite(u[n])) return fail(PULBM_EDIVERGED, "non-finite initial u at entry %zu", n);
+    mean /= (double)N;
+    if (c->p.phi_ref < 0) codec_constants(c->p, mean > 0.5 ? 1.0 : 0.0, c->h);
+    c->h.step = 0;
+    c->h.step_end = INT64_MAX;
+    int rc = upload_desc(c);
+    if (rc) return rc;
+    double* tmp = nullptr;
+    const size_t bytes = (2 + (size_t)dim) * N * sizeof(double);
+    HIPC(hipMalloc((void**)&tmp, bytes));
+    hipError_t e = hipMemcpyAsync(tmp, phi, N * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(tmp + N, P, N * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(tmp + 2 * N, u, (size_t)dim * N * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) {
+        launch_init(dim, c->p.store, c->stream, c->tab, c->tstart, c->ntiles, tmp, tmp + N, tmp + 2 * N);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return fail(PULBM_EDEVICE, "init failed: %s", hipGetErrorString(e));
+    c->step = 0;
+    c->ready = true;
+    return PULBM_OK;
+}
+
+static int queue_steps(pulbm_case* c, int64_t nsteps)
+{
+    for (int64_t s = 0; s < nsteps;) {
+        const int chunk = (int)std::min<int64_t>(nsteps - s, 1 << 20);
+        for (int k = 0; k < chunk; ++k)
+            for (int w = 0; w < 3; ++w) launch(c->p.dim, c->p.store, c->stream, c->tab, c->tstart, 1, c->ntiles, k, w);
+        hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, c->stream, c->tab, 1, chunk);
+        HIPC(hipGetLastError());
+        s += chunk;
+    }
+    c->step += nsteps;
+    c->h.step = c->step;
+    return PULBM_OK;
+}
+
+extern "C" int pulbm_step(pulbm_case* c, int64_t nsteps)
+{
+    if (!c) return fail(PULBM_EINVAL, "case is NULL");
+    if (!c->ready) return fail(PULBM_ESTATE, "pulbm_step before pulbm_init_fields");
+    if (nsteps < 0) return fail(PULBM_EINVAL, "nsteps < 0");
+    return queue_steps(c, nsteps);
+}
+
+extern "C" int pulbm_step_timed(pulbm_case* c, int64_t nsteps, double* ms)
+{
+    if (!c || !ms) return fail(PULBM_EINVAL, "NULL argument");
+    if (!c->ready) return fail(PULBM_ESTATE, "pulbm_step_timed before pulbm_init_fields");
+    hipEvent_t ev[4];
+    for (int k = 0; k < 4; ++k) HIPC(hipEventCreate(&ev[k]));
+    int rc = PULBM_OK;
+    for (int64_t s = 0; s < nsteps && rc == PULBM_OK; ++s) {
+        (void)hipEventRecord(ev[0], c->stream);
+        for (int w = 0; w < 3; ++w) {
+            launch(c->p.dim, c->p.store, c->stream, c->tab, c->tstart, 1, c->ntiles, 0, w);
+            (void)hipEventRecord(ev[w + 1], c->stream);
+        }
+        hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, c->stream, c->tab, 1, 1);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess) e = hipEventSynchronize(ev[3]);
+        if (e != hipSuccess) {
+            rc = fail(PULBM_EDEVICE, "timed step failed: %s", hipGetErrorString(e));
+            break;
+        }
+        for (int w = 0; w < 3; ++w) {
+            float t = 0.f;
+            (void)hipEventElapsedTime(&t, ev[w], ev[w + 1]);
+            ms[w] += t;
+        }
+        c->step += 1;
+    }
+    c->h.step = c->step;
+    for (int k = 0; k < 4; ++k) (void)hipEventDestroy(ev[k]);
+    if (rc == PULBM_OK) HIPC(hipStreamSynchronize(c->stream));
+    return rc;
+}
+
+extern "C" int pulbm_read_fields(pulbm_case* c, double* phi, double* P, double* u)
+{
+    if (!c) return fail(PULBM_EINVAL, "case is NULL");
+    if (!c->ready) return fail(PULBM_ESTATE, "read before init");
+    int rc = read_pass(c);
+    if (rc) return rc;
+    const size_t N = (size_t)c->h.N;
+    if ((rc = fetch(c, c->h.phi, phi, N))) return rc;
+    if ((rc = fetch(c, c->h.P[(c->step + 1) & 1], P, N))) return rc;
+    if ((rc = fetch(c, c->h.U, u, (size_t)c->p.dim * N))) return rc;
+    return PULBM_OK;
+}
+
+extern "C" int pulbm_diagnostics(pulbm_case* c, pulbm_diag* d)
+{
+    if (!c || !d) return fail(PULBM_EINVAL, "NULL argument");
+    if (!c->ready) return fail(PULBM_ESTATE, "diagnostics before init");
+    int rc = read_pass(c);
+    if (rc) return rc;
+    double* partial = (double*)(c->base + c->L.partial);
+    double* dd = (double*)(c->base + c->L.diag);
+    if (c->p.store == PULBM_STORE_FP64)
+        hipLaunchKernelGGL(k_diag<double>, dim3(kDiagBlocks), dim3(256), 0, c->stream, c->d, partial);
+    else
+        hipLaunchKernelGGL(k_diag<float>, dim3(kDiagBlocks), dim3(256), 0, c->stream, c->d, partial);
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, c->stream, partial, kDiagBlocks, dd);
+    HIPC(hipGetLastError());
+    double r[kDiagVals];
+    HIPC(hipMemcpyAsync(r, dd, sizeof r, hipMemcpyDeviceToHost, c->stream));
+    HIPC(hipStreamSynchronize(c->stream));
+    std::memset(d, 0, sizeof *d);
+    d->phi_sum = r[0];
+    for (int a = 0; a < 3; ++a) { d->u_sum[a] = r[1 + a]; d->rhou_sum[a] = r[4 + a]; }
+    d->umax = r[7];
+    d->nonfinite = (int64_t)r[8];
+    d->step = c->step;
+    if (d->nonfinite > 0) return fail(PULBM_EDIVERGED, "%lld nodes hold non-finite values", (long long)d->nonfinite);
+    return PULBM_OK;
+}
+
+// Restart image: header, h, g, previous-step pressure.
+namespace {
+struct CkptHeader {
+    char magic[8];
+    int32_t version, store;
+    pulbm_params p;
+    int64_t step;
+    double phi_ref;
+    uint64_t h_bytes, g_bytes, P_bytes;
+};
+}  // namespace
+
+extern "C" int pulbm_checkpoint_bytes(const pulbm_case* c, size_t* bytes)
+{
+    if (!c || !bytes) return fail(PULBM_EINVAL, "NULL argument");
+    const size_t N = (size_t)c->h.N, sb = store_bytes(c->p.store), ab = aux_bytes(c->p.store);
+    *bytes = sizeof(CkptHeader) + (size_t)(c->p.q_phase + c->p.q_hydro) * N * sb + N * ab;
+    return PULBM_OK;
+}
+
+extern "C" int pulbm_checkpoint(pulbm_case* c, void* buf, size_t bytes)
+{
+    size_t need = 0;
+    int rc = pulbm_checkpoint_bytes(c, &need);
+    if (rc) return rc;
+    if (!buf || bytes < need) return fail(PULBM_EINVAL, "checkpoint buffer needs %zu bytes", need);
+    if (!c->ready) return fail(PULBM_ESTATE, "checkpoint before init");
+    const size_t N = (size_t)c->h.N, sb = store_bytes(c->p.store), ab = aux_bytes(c->p.store);
+    CkptHeader hd;
+    std::memset(&hd, 0, sizeof hd);
+    std::memcpy(hd.magic, "PULBMCK1", 8);
+    hd.version = 1;
+    hd.store = c->p.store;
+    hd.p = c->p;
+    hd.step = c->step;
+    hd.phi_ref = c->h.phi_ref;
+    hd.h_bytes = (uint64_t)c->p.q_phase * N * sb;
+    hd.g_bytes = (uint64_t)c->p.q_hydro * N * sb;
+    hd.P_bytes = N * ab;
+    char* o = (char*)buf;
+    std::memcpy(o, &hd, sizeof hd);
+    o += sizeof hd;
+    HIPC(hipMemcpyAsync(o, c->h.h, hd.h_bytes, hipMemcpyDeviceToHost, c->stream));
+    o += hd.h_bytes;
+    HIPC(hipMemcpyAsync(o, c->h.g, hd.g_bytes, hipMemcpyDeviceToHost, c->stream));
+    o += hd.g_bytes;
+    HIPC(hipMemcpyAsync(o, c->h.P[c->step & 1], hd.P_bytes, hipMemcpyDeviceToHost, c->stream));
+    HIPC(hipStreamSynchronize(c->stream));
+    return PULBM_OK;
+}
+
+extern "C" int pulbm_restore(pulbm_case* c, const void* buf, size_t bytes)
+{
+    if (!c || !buf) return fail(PULBM_EINVAL, "NULL argument");
+    if (bytes < sizeof(CkptHeader)) return fail(PULBM_EINVAL, "restart image too short");
+    CkptHeader hd;
+    std::memcpy(&hd, buf, sizeof hd);
+    if (std::memcmp(hd.magic, "PULBMCK1", 8) || hd.version != 1) return fail(PULBM_EINVAL, "not a restart image");
+    const pulbm_params& q = hd.p;
+    const pulbm_params& p = c->p;
+    if (q.dim != p.dim || q.nx != p.nx || q.ny != p.ny || q.nz != p.nz || q.store != p.store ||
+        q.q_hydro != p.q_hydro || q.q_phase != p.q_phase)
+        return fail(PULBM_EINVAL, "restart image is for a different grid or precision");
+    size_t need = 0;
+    pulbm_checkpoint_bytes(c, &need);
+    if (bytes < need) return fail(PULBM_EINVAL, "restart image too short");
+    c->step = hd.step;
+    c->h.step = hd.step;
+    c->h.step_end = INT64_MAX;
+    c->h.phi_ref = hd.phi_ref;
+    int rc = upload_desc(c);
+    if (rc) return rc;
+    const char* o = (const char*)buf + sizeof hd;
+    HIPC(hipMemcpyAsync(c->h.h, o, hd.h_bytes, hipMemcpyHostToDevice, c->stream));
+    o += hd.h_bytes;
+    HIPC(hipMemcpyAsync(c->h.g, o, hd.g_bytes, hipMemcpyHostToDevice, c->stream));
+    o += hd.g_bytes;
+    HIPC(hipMemcpyAsync(c->h.P[c->step & 1], o, hd.P_bytes, hipMemcpyHostToDevice, c->stream));
+    HIPC(hipStreamSynchronize(c->stream));
+    c->ready = true;
+    return PULBM_OK;
+}
+
+extern "C" int pulbm_sync(pulbm_case* c)
+{
+    if (!c) return fail(PULBM_EINVAL, "case is NULL");
+    HIPC(hipStreamSynchronize(c->stream));
+    return PULBM_OK;
+}
+
+extern "C" int64_t pulbm_steps_done(const pulbm_case* c) { return c ? c->step : -1; }
+
+// ============================================================= serving batch
+
+struct pulbm_batch {
+    size_t budget = 0, used = 0;
+    int store = 0, max_slots = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    struct Slot {
+        pulbm_case* c = nullptr;
+        int64_t end = 0;
+        size_t bytes = 0;
+    };
+    std::vector<Slot> slots;
+    // per lattice dimension: device table of case pointers + tile starts
+    struct Tab {
+        CaseDev** dtab = nullptr;
+        int* dts = nullptr;
+        int cap = 0, ncases = 0, tiles = 0;
+        std::map<int, hipGraphExec_t> graphs;  // by ksteps
+    } tab[2];
+    bool dirty = true;
+};
+
+namespace {
+
+void drop_graphs(pulbm_batch::Tab& t)
+{
+    for (auto& kv : t.graphs) (void)hipGraphExecDestroy(kv.second);
+    t.graphs.clear();
+}
+
+int rebuild_tables(pulbm_batch* b)
+{
+    HIPC(hipStreamSynchronize(b->stream));
+    for (int di = 0; di < 2; ++di) {
+        const int dim = di + 2;
+        pulbm_batch::Tab& t = b->tab[di];
+        drop_graphs(t);
+        std::vector<CaseDev*> ptr;
+        std::vector<int> ts{0};
+        for (auto& s : b->slots)
+            if (s.c && s.c->p.dim == dim) {
+                ptr.push_back(s.c->d);
+                ts.push_back(ts.back() + s.c->ntiles);
+            }
+        t.ncases = (int)ptr.size();
+        t.tiles = ts.back();
+        if (t.ncases == 0) continue;
+        if (t.cap < t.ncases) {
+            if (t.dtab) (void)hipFree(t.dtab);
+            if (t.dts) (void)hipFree(t.dts);
+            t.dtab = nullptr;
+            t.dts = nullptr;
+            t.cap = std::max(t.ncases, b->max_slots);
+            HIPC(hipMalloc((void**)&t.dtab, t.cap * sizeof(CaseDev*)));
+            HIPC(hipMalloc((void**)&t.dts, (t.cap + 1) * sizeof(int)));
+        }
+        HIPC(hipMemcpyAsync(t.dtab, ptr.data(), t.ncases * sizeof(CaseDev*), hipMemcpyHostToDevice, b->stream));
+        HIPC(hipMemcpyAsync(t.dts, ts.data(), (t.ncases + 1) * sizeof(int), hipMemcpyHostToDevice, b->stream));
+    }
+    HIPC(hipStreamSynchronize(b->stream));
+    b->dirty = false;
+    return PULBM_OK;
+}
+
+}  // namespace
+
+extern "C" int pulbm_batch_create(size_t budget, int32_t store, int32_t max_slots, void* hip_stream,
+                                  pulbm_batch** out)
+{
+    if (!out) return fail(PULBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (store < PULBM_STORE_FP64 || store > PULBM_STORE_BF16) return fail(PULBM_EINVAL, "bad store");
+    if (max_slots < 1 || max_slots > 4096) return fail(PULBM_EINVAL, "max_slots must be in [1, 4096]");
+    pulbm_batch* b = new (std::nothrow) pulbm_batch();
+    if (!b) return fail(PULBM_ENOMEM, "host allocation failed");
+    b->budget = budget;
+    b->store = store;
+    b->max_slots = max_slots;
+    b->stream = (hipStream_t)hip_stream;
+    if (!b->stream) {  // graph capture needs a stream other than the null stream
+        hipError_t e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            delete b;
+            return fail(PULBM_EDEVICE, "hipStreamCreate failed: %s", hipGetErrorString(e));
+        }
+        b->own_stream = true;
+    }
+    b->slots.resize(max_slots);
+    *out = b;
+    return PULBM_OK;
+}
+
+extern "C" int pulbm_batch_admit(pulbm_batch* b, const pulbm_params* p, const double* phi, const double* P,
+                                 const double* u, int64_t nsteps, int32_t* slot)
+{
+    if (!b || !slot) return fail(PULBM_EINVAL, "NULL argument");
+    int rc = validate(p);
+    if (rc) return rc;
+    if (p->store != b->store) return fail(PULBM_EINVAL, "case store %d differs from the batch's %d", p->store, b->store);
+    if (nsteps < 0) return fail(PULBM_EINVAL, "nsteps < 0");
+    const size_t bytes = make_layout(*p).total;
+    int free_slot = -1;
+    for (int i = 0; i < b->max_slots; ++i)
+        if (!b->slots[i].c) { free_slot = i; break; }
+    if (free_slot < 0) return fail(PULBM_EAGAIN, "no free slot");
+    if (b->used + bytes > b->budget) return fail(PULBM_EAGAIN, "needs %zu bytes, %zu of %zu free", bytes, b->budget - b->used, b->budget);
+    pulbm_case* c = nullptr;
+    if ((rc = pulbm_create(p, nullptr, 0, b->stream, &c))) return rc;
+    if ((rc = pulbm_init_fields(c, phi, P, u))) {
+        pulbm_destroy(c);
+        return rc;
+    }
+    c->h.step_end = nsteps;
+    if ((rc = upload_desc(c))) {
+        pulbm_destroy(c);
+        return rc;
+    }
+    b->slots[free_slot].c = c;
+    b->slots[free_slot].end = nsteps;
+    b->slots[free_slot].bytes = bytes;
+    b->used += bytes;
+    b->dirty = true;
+    *slot = free_slot;
+    return PULBM_OK;
+}
+
+extern "C" int pulbm_batch_advance(pulbm_batch* b, int32_t ksteps)
+{
+    if (!b) return fail(PULBM_EINVAL, "batch is NULL");
+    if (ksteps < 1 || ksteps > 4096) return fail(PULBM_EINVAL, "ksteps must be in [1, 4096]");
+    if (b->dirty) {
+        int rc = rebuild_tables(b);
+        if (rc) return rc;
+    }
+    for (int di = 0; di < 2; ++di) {
+        pulbm_batch::Tab& t = b->tab[di];
+        if (t.ncases == 0) continue;
+        auto it = t.graphs.find(ksteps);
+        if (it == t.graphs.end()) {
+            hipGraph_t g = nullptr;
+            hipGraphExec_t ge = nullptr;
+            HIPC(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+            for (int k = 0; k < ksteps; ++k)
+                for (int w = 0; w < 3; ++w) launch(di + 2, b->store, b->stream, t.dtab, t.dts, t.ncases, t.tiles, k, w);
+            hipLaunchKernelGGL(k_advance, dim3((t.ncases + 63) / 64), dim3(64), 0, b->stream, t.dtab, t.ncases, ksteps);
+            HIPC(hipStreamEndCapture(b->stream, &g));
+            HIPC(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+            (void)hipGraphDestroy(g);
+            it = t.graphs.emplace(ksteps, ge).first;
+        }
+        HIPC(hipGraphLaunch(it->second, b->stream));
+    }
+    // host bookkeeping of every resident case
+    for (auto& s : b->slots)
+        if (s.c) {
+            s.c->step = std::min<int64_t>(s.c->step + ksteps, s.end);
+            s.c->h.step = s.c->step;
+        }
+    return PULBM_OK;
+}
+
+extern "C" int pulbm_batch_poll(pulbm_batch* b, int32_t* done, int32_t cap, int32_t* ndone)
+{
+    if (!b || !ndone) return fail(PULBM_EINVAL, "NULL argument");
+    HIPC(hipStreamSynchronize(b->stream));
+    int k = 0;
+    for (int i = 0; i < b->max_slots; ++i)
+        if (b->slots[i].c && b->slots[i].c->step >= b->slots[i].end) {
+            if (done && k < cap) done[k] = i;
+            ++k;
+        }
+    *ndone = k;
+    return PULBM_OK;
+}
+
+extern "C" int pulbm_batch_take(pulbm_batch* b, int32_t slot, double* phi, double* P, double* u)
+{
+    if (!b || slot < 0 || slot >= b->max_slots || !b->slots[slot].c) return fail(PULBM_EINVAL, "bad slot");
+    pulbm_batch::Slot& s = b->slots[slot];
+    HIPC(hipStreamSynchronize(b->stream));
+    // leaving the batch: lift the step limit so the read pass runs at any step
+    s.c->h.step_end = INT64_MAX;
+    int rc = upload_desc(s.c);
+    if (rc) return rc;
+    rc = pulbm_read_fields(s.c, phi, P, u);
+    if (rc) return rc;
+    pulbm_destroy(s.c);
+    b->used -= s.bytes;
+    s = pulbm_batch::Slot();
+    b->dirty = true;
+    return PULBM_OK;
+}
+
+extern "C" int pulbm_batch_usage(const pulbm_batch* b, size_t* used, int32_t* active)
+{
+    if (!b) return fail(PULBM_EINVAL, "batch is NULL");
+    if (used) *used = b->used;
+    if (active) {
+        int a = 0;
+        for (auto& s : b->slots) a += s.c != nullptr;
+        *active = a;
+    }
+    return PULBM_OK;
+}
+
+extern "C" void pulbm_batch_destroy(pulbm_batch* b)
+{
+    if (!b) return;
+    (void)hipStreamSynchronize(b->stream);
+    for (auto& s : b->slots)
+        if (s.c) pulbm_destroy(s.c);
+    for (auto& t : b->tab) {
+        drop_graphs(t);
+        if (t.dtab) (void)hipFree(t.dtab);
+        if (t.dts) (void)hipFree(t.dts);
+    }
+    if (b->own_stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}

@@ -1,0 +1,199 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU reference
+on the same seeded inputs.
+
+FP64 storage must agree with the reference to 1e-10 relative, field by field
+(max |gpu - ref| / max |ref|, with a floor of 1e-12 on the scale of u and of P
+variations).  The cases cover both lattices, several tiles with ragged tails
+in every axis, periodic and walled boxes, gravity, and the degenerate grids
+(one node thick along an axis).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2512_01027_amd import binding as B
+from paper_2512_01027_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+
+
+def _fields(cfg, seed=5, R=None):
+    dim = cfg["dim"]
+    if R is None:
+        R = 0.28 * min(cfg["nx"], cfg["ny"], cfg["nz"] if dim == 3 else 10 ** 9)
+    c = (cfg["nx"] * 0.47, cfg["ny"] * 0.53, cfg["nz"] * 0.45)
+    phi, P, u = W.droplet(cfg, R, center=c)
+    phi = np.clip(phi + W.random_smooth(cfg, seed, amp=0.02), 0, 1)
+    for a in range(dim):
+        u[a] += W.random_smooth(cfg, seed + 1 + a, amp=0.01)
+    P += W.random_smooth(cfg, seed + 9, amp=1e-3)
+    return phi, P, u
+
+
+def _rel(a, b, floor):
+    return np.abs(a - b).max() / max(np.abs(b).max(), floor)
+
+
+def _compare(gpu, ref, tol, tag=""):
+    (pg, Pg, ug), (pr, Pr, ur) = gpu, ref
+    e_phi = _rel(pg, pr, 1e-12)
+    e_P = np.abs((Pg - Pg.mean()) - (Pr - Pr.mean())).max() / max(np.abs(Pr - Pr.mean()).max(), 1e-12)
+    e_Pabs = np.abs(Pg - Pr).max() / max(np.abs(Pr).max(), 1e-12)
+    e_u = _rel(ug, ur, 1e-12)
+    msg = f"{tag} phi {e_phi:.2e} P {e_P:.2e} (abs {e_Pabs:.2e}) u {e_u:.2e}"
+    print(msg, flush=True)
+    assert e_phi < tol and e_P < tol and e_Pabs < tol and e_u < tol, msg
+
+
+CASES = {
+    "2d_periodic_ragged": dict(dim=2, nx=70, ny=37),
+    "2d_walls_gravity": dict(dim=2, nx=45, ny=30, wall=(1, 1, 0), gravity=(2e-6, -1e-5, 0.0)),
+    "2d_channel_x": dict(dim=2, nx=20, ny=9, wall=(1, 0, 0), gravity=(0.0, 5e-6, 0.0)),
+    "3d_periodic_ragged": dict(dim=3, nx=37, ny=10, nz=7),
+    "3d_walls_z_gravity": dict(dim=3, nx=33, ny=9, nz=8, wall=(0, 0, 1), gravity=(0.0, 0.0, -1e-5)),
+    "3d_all_walls": dict(dim=3, nx=20, ny=7, nz=9, wall=(1, 1, 1), gravity=(1e-6, 2e-6, -1e-5)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_fp64_matches_oracle(name):
+    kw = dict(CASES[name])
+    dim, nx, ny = kw.pop("dim"), kw.pop("nx"), kw.pop("ny")
+    nz = kw.pop("nz", 1)
+    cfg = W.base_case(dim, nx, ny, nz, nu_heavy=0.05, nu_light=0.15, sigma=0.01, store="fp64", **kw)
+    f = _fields(cfg)
+    g = B.Case(cfg)
+    g.init_fields(*f)
+    o = oracle.OracleCase(cfg)
+    o.init_fields(*f)
+    _compare(g.read_fields(), o.read_fields(), TOL64, name + " step 0")
+    for steps in (1, 6, 23):
+        g.step(steps - g.steps_done)
+        o.step(steps - o.diagnostics()["step"])
+        _compare(g.read_fields(), o.read_fields(), TOL64, f"{name} step {steps}")
+    dg, do = g.diagnostics(), o.diagnostics()
+    assert dg["nonfinite"] == 0 and dg["step"] == do["step"]
+    assert abs(dg["phi_sum"] - do["phi_sum"]) < 1e-11 * abs(do["phi_sum"])
+    for a in range(dim):
+        assert abs(dg["u_sum"][a] - do["u_sum"][a]) < 1e-10 * g.N * max(do["umax"], 1e-12)
+        assert abs(dg["rhou_sum"][a] - do["rhou_sum"][a]) < 1e-10 * g.N * 1e3 * max(do["umax"], 1e-12)
+    assert abs(dg["umax"] - do["umax"]) < 1e-10 * do["umax"]
+
+
+@pytest.mark.parametrize("shape", [(1, 5, 1), (6, 1, 1), (5, 4, 1), (3, 1, 4), (1, 1, 5)])
+def test_degenerate_thin_grids(shape):
+    """Grids one node thick along an axis (periodic self-neighbours)."""
+    nx, ny, nz = shape
+    dim = 2 if nz == 1 else 3
+    cfg = W.base_case(dim, nx, ny, nz, nu_heavy=0.05, nu_light=0.15, store="fp64")
+    f = _fields(cfg, R=1.2)
+    g = B.Case(cfg)
+    g.init_fields(*f)
+    o = oracle.OracleCase(cfg)
+    o.init_fields(*f)
+    g.step(5)
+    o.step(5)
+    _compare(g.read_fields(), o.read_fields(), TOL64, f"thin {shape}")
+
+
+def _errs(a, b, p_scale, u_scale):
+    """Max differences relative to the field scale: phi's range, the Laplace
+    pressure sigma/R for P (P0 = 0, so P itself starts at zero), and
+    max(|u|, u_scale) for the spurious velocity."""
+    (pa, Pa, ua), (pb, Pb, ub) = a, b
+    return (np.abs(pa - pb).max() / np.abs(pb).max(),
+            np.abs(Pa - Pb).max() / max(np.abs(Pb - Pb.mean()).max(), p_scale),
+            np.abs(ua - ub).max() / max(np.abs(ub).max(), u_scale))
+
+
+def test_static_droplet_2d_config_full_run():
+    """The 2D 64x64 static droplet (rho ratio 1000, R = 16, sigma 0.01) over its
+    full 2000 steps.  Where |grad phi| falls below the normal's epsilon (1e-10)
+    at the droplet centre, n = grad phi / (|grad phi| + eps) amplifies rounding
+    noise about 50x per step until |grad phi| ~ eps, so two exact
+    implementations cannot agree to 1e-10 over thousands of steps.  The bar is
+    the reference's own sensitivity: the GPU must be within 3x the difference
+    between the reference and the reference fed a 1e-15 relative perturbation
+    of phi0 (and within 1e-10 while that envelope is below it), plus Laplace dP,
+    phi-mass and spurious velocity."""
+    cfg, f, steps = W.config_static_droplet_2d()
+    g = B.Case(cfg)
+    g.init_fields(*f)
+    o = oracle.OracleCase(cfg)
+    o.init_fields(*f)
+    rng = np.random.default_rng(0)
+    o2 = oracle.OracleCase(cfg)
+    o2.init_fields(f[0] * (1 + 1e-15 * rng.standard_normal(f[0].shape)), f[1], f[2])
+    done = 0
+    for s in (1, 3, 100, steps):
+        g.step(s - done)
+        o.step(s - done)
+        o2.step(s - done)
+        done = s
+        ref = o.read_fields()
+        eg = _errs(g.read_fields(), ref, 0.01 / 16, 1e-6)
+        ee = _errs(o2.read_fields(), ref, 0.01 / 16, 1e-6)
+        print(f"step {s}: gpu-ref {eg}, ref-envelope {ee}", flush=True)
+        for k in range(3):
+            assert eg[k] < max(1e-10, 3 * ee[k]), (s, k, eg, ee)
+    gr = g.read_fields()
+    dg, do = g.diagnostics(), o.diagnostics()
+    m0 = f[0].sum()
+    assert abs(dg["phi_sum"] - m0) < 1e-12 * m0
+    assert abs(dg["umax"] - do["umax"]) < 0.05 * do["umax"]
+    phi, P, _ = gr
+    dP = P[phi > 0.99].mean() - P[phi < 0.01].mean()
+    assert abs(dP - 0.01 / 16) < 0.05 * 0.01 / 16
+
+
+@pytest.mark.parametrize("store,tol", [("fp32", 2e-5)])
+@pytest.mark.parametrize("case", ["3d_walls_z_gravity", "2d_walls_gravity"])
+def test_fp32_matches_oracle(store, tol, case):
+    kw = dict(CASES[case])
+    dim, nx, ny = kw.pop("dim"), kw.pop("nx"), kw.pop("ny")
+    nz = kw.pop("nz", 1)
+    cfg = W.base_case(dim, nx, ny, nz, nu_heavy=0.05, nu_light=0.15, store=store, **kw)
+    f = _fields(cfg)
+    g = B.Case(cfg)
+    g.init_fields(*f)
+    o = oracle.OracleCase(cfg)
+    o.init_fields(*f)
+    g.step(20)
+    o.step(20)
+    _compare(g.read_fields(), o.read_fields(), tol, f"{case} {store}")
+
+
+def test_checkpoint_restart_bitwise():
+    cfg = W.base_case(3, 21, 9, 10, wall=(0, 0, 1), gravity=(0, 0, -1e-5), store="fp32")
+    f = _fields(cfg)
+    a = B.Case(cfg)
+    a.init_fields(*f)
+    a.step(30)
+    b = B.Case(cfg)
+    b.init_fields(*f)
+    b.step(13)
+    blob = b.checkpoint()
+    c = B.Case(cfg)
+    c.restore(blob)
+    c.step(17)
+    for x, y in zip(a.read_fields(), c.read_fields()):
+        assert np.array_equal(x, y)
+
+
+def test_nonfinite_input_rejected_and_invalid_params():
+    cfg = W.base_case(2, 16, 16, store="fp64")
+    phi, P, u = W.droplet(cfg, 4.0)
+    phi[0, 3, 3] = np.nan
+    g = B.Case(cfg)
+    with pytest.raises(B.PulbmError) as e:
+        g.init_fields(phi, P, u)
+    assert e.value.code == B.EDIVERGED
+    with pytest.raises(B.PulbmError) as e:
+        g.step(1)
+    assert e.value.code == B.ESTATE
+    for bad in (dict(nu_heavy=-0.1), dict(W=0.0), dict(rho_heavy=0.5), dict(store="bogus")):
+        c2 = dict(cfg, **bad)
+        with pytest.raises((B.PulbmError, KeyError)):
+            B.Case(c2)
