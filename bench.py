@@ -25,17 +25,20 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 # Algorithmic bytes per node of each kernel, 3D D3Q27 + D3Q19 (values per node
-# times the storage width): moments reads 46 populations and writes
-# phi, u*(3), S, M2(6); pressure reads u*(3), P, phi, S and writes P;
-# collide reads P, phi, u*(3), M2(6), h(19) and writes 46 populations.
+# times their width, each read or written once): moments reads 46 populations
+# and writes phi, u*(3), S, M2(6); pressure reads u*(3), P, phi, S and writes
+# P; velocity reads P, u*(3), phi and writes u(3); collide reads phi, u(3),
+# M2(6), h(19) and writes 46 populations.
 POP_VALUES_3D = 46
+KERNELS = ("moments", "pressure", "velocity", "collide")
 
 
 def kernel_bytes(store_bytes, aux_bytes=4):
     return {
         "moments": POP_VALUES_3D * store_bytes + 11 * aux_bytes,
         "pressure": 7 * aux_bytes,
-        "collide": 19 * store_bytes + 11 * aux_bytes + POP_VALUES_3D * store_bytes,
+        "velocity": 8 * aux_bytes,
+        "collide": 19 * store_bytes + 10 * aux_bytes + POP_VALUES_3D * store_bytes,
     }
 
 
@@ -91,7 +94,25 @@ def main():
     ap.add_argument("--n", type=int, default=128, help="grid edge of the 3D droplet workload")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp16", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+
+        src = torch.ones(args.copy_probe * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 5
+        nbytes = src.numel() * 4
+        print(json.dumps({"copy_probe_bytes": nbytes, "dispatches": 6,
+                          "copy_GBs_read_plus_write": round(2 * nbytes / dt / 1e9, 1)}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
@@ -103,7 +124,7 @@ def main():
     dt, ms, diag = run_gpu(cfg, fields, args.steps, args.warmup)
     mlups = N * args.steps / dt / 1e6
     kb = kernel_bytes(4)
-    ach = kb["collide"] * N / (ms[2] * 1e-3) / 1e9
+    ach = kb["collide"] * N / (ms[3] * 1e-3) / 1e9
     out = {
         "metric": "coupled-lattice MLUPS (D3Q27 hydro + D3Q19 phase field)",
         "value": round(mlups, 2),
@@ -122,7 +143,8 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "k_collide", "achieved": round(ach, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
                      "traffic": None},
-        "kernel_ms": {"moments": round(ms[0], 4), "pressure": round(ms[1], 4), "collide": round(ms[2], 4)},
+        "kernel_ms": {k: round(float(v), 4) for k, v in zip(KERNELS, ms)},
+        "kernel_GBs": {k: round(kb[k] * N / (float(v) * 1e-3) / 1e9, 1) for k, v in zip(KERNELS, ms)},
         "effective_state_GBs": round(mlups * 1e6 * state_bytes(4) / 1e9, 1),
         "nonfinite": diag["nonfinite"],
     }
@@ -131,7 +153,7 @@ def main():
         dt16, ms16, _ = run_gpu(cfg16, fields, args.steps, args.warmup)
         out["fp16_store"] = {"value": round(N * args.steps / dt16 / 1e6, 2), "unit": "MLUPS",
                              "ratio_vs_fp32": round(dt / dt16, 3),
-                             "kernel_ms": [round(x, 4) for x in ms16]}
+                             "kernel_ms": {k: round(float(v), 4) for k, v in zip(KERNELS, ms16)}}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, fields)
     print(json.dumps(out))

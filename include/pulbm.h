@@ -89,13 +89,13 @@ int pulbm_create(const pulbm_params* p, void* dev_arena, size_t arena_bytes, voi
  * distributions start at equilibrium; the previous-step pressure is P). */
 int pulbm_init_fields(pulbm_case* c, const double* phi, const double* P, const double* u);
 
-/* Queue nsteps coupled steps (moments, pressure, collide+stream) on the
- * case's stream.  Returns without waiting. */
+/* Queue nsteps coupled steps (moments, pressure, velocity, collide+stream)
+ * on the case's stream.  Returns without waiting. */
 int pulbm_step(pulbm_case* c, int64_t nsteps);
 
-/* Like pulbm_step, but waits and adds the GPU time of each of the three
- * kernels (moments, pressure, collide) to ms[0..2] (HIP events on the case's
- * stream around every launch). */
+/* Like pulbm_step, but waits and adds the GPU time of each of the four
+ * kernels (moments, pressure, velocity, collide+stream) to ms[0..3] (HIP
+ * events on the case's stream around every launch). */
 int pulbm_step_timed(pulbm_case* c, int64_t nsteps, double* ms);
 
 /* phi[N], P[N], u[dim*N] of the current state: the moment stage applied to

@@ -204,7 +204,8 @@ class Case:
         _check(self.lib.pulbm_step(self._h, int(n)))
 
     def step_timed(self, n: int):
-        ms = np.zeros(3)
+        """GPU milliseconds of the moments, pressure, velocity and collide kernels."""
+        ms = np.zeros(4)
         _check(self.lib.pulbm_step_timed(self._h, int(n), _dp(ms)))
         return ms
 

@@ -13,10 +13,6 @@
 
 namespace pulbm {
 
-struct bf16_t {
-    uint16_t bits;
-};
-
 __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f)
 {
     uint32_t u = __float_as_uint(f);
@@ -26,45 +22,49 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f)
 }
 __device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
+#define PULBM_GLB __attribute__((address_space(1)))
+#define PULBM_CST __attribute__((address_space(4)))
+
 template <class S> struct Codec;
 
 template <> struct Codec<double> {
     using CT = double;  // compute type
     static constexpr int BYTES = 8;
-    __device__ static __forceinline__ double load(const double* p, size_t i, double, double) { return p[i]; }
-    __device__ static __forceinline__ void store(double* p, size_t i, double v, double, double) { p[i] = v; }
+    __device__ static __forceinline__ double dec(double v, double, double) { return v; }
+    __device__ static __forceinline__ double enc(double v, double, double) { return v; }
 };
 
 template <> struct Codec<float> {
     using CT = float;
     static constexpr int BYTES = 4;
-    __device__ static __forceinline__ float load(const float* p, size_t i, float, float) { return p[i]; }
-    __device__ static __forceinline__ void store(float* p, size_t i, float v, float, float) { p[i] = v; }
+    __device__ static __forceinline__ float dec(float v, float, float) { return v; }
+    __device__ static __forceinline__ float enc(float v, float, float) { return v; }
 };
 
 template <> struct Codec<_Float16> {
     using CT = float;
     static constexpr int BYTES = 2;
-    __device__ static __forceinline__ float load(const _Float16* p, size_t i, float inv_scale, float shift)
+    __device__ static __forceinline__ float dec(_Float16 v, float inv_scale, float shift)
     {
-        return fmaf((float)p[i], inv_scale, shift);
+        return fmaf((float)v, inv_scale, shift);
     }
-    __device__ static __forceinline__ void store(_Float16* p, size_t i, float v, float scale, float shift)
+    __device__ static __forceinline__ _Float16 enc(float v, float scale, float shift)
     {
-        p[i] = (_Float16)((v - shift) * scale);
+        return (_Float16)((v - shift) * scale);
     }
 };
 
-template <> struct Codec<bf16_t> {
+// BF16 storage: the upper 16 bits of a binary32, held in a uint16_t.
+template <> struct Codec<uint16_t> {
     using CT = float;
     static constexpr int BYTES = 2;
-    __device__ static __forceinline__ float load(const bf16_t* p, size_t i, float inv_scale, float shift)
+    __device__ static __forceinline__ float dec(uint16_t v, float inv_scale, float shift)
     {
-        return fmaf(bf16_to_f32(p[i].bits), inv_scale, shift);
+        return fmaf(bf16_to_f32(v), inv_scale, shift);
     }
-    __device__ static __forceinline__ void store(bf16_t* p, size_t i, float v, float scale, float shift)
+    __device__ static __forceinline__ uint16_t enc(float v, float scale, float shift)
     {
-        p[i].bits = f32_to_bf16_rne((v - shift) * scale);
+        return f32_to_bf16_rne((v - shift) * scale);
     }
 };
 

@@ -1,18 +1,19 @@
 // Kernels of the coupled phase-field + P-u lattice Boltzmann step
 // (Otomo et al., arXiv 2512.01027, Sec. II) for gfx950.
 //
-// One time step is three launches over every resident case:
-//   k_moments  per node, no halo: gathers h and g (AA pattern), writes
+// One time step is four launches over every resident case:
+//   k_moments  per node, no halo: gathers h and g (AA pattern) and writes
 //              phi = sum h, u* = sum g c, S = rho_ref T sum g (without the
 //              pressure carried by the rest population) and M2 = sum g c c.
 //   k_pressure 1-halo LDS tile, FP64 arithmetic: the pressure formula of
 //              Sec. II with K_i of the previous-step pressure and, in the
 //              omega term, u* at x - c_i.
-//   k_collide  LDS tiles (P with a 2-node halo, phi and u* with 1): rebuilds
-//              u = u* + sum K_i c_i with the new P, takes the isotropic
-//              central differences of phi, rho and u, applies the BGK
-//              phase-field collision and the filter collision of the
-//              hydrodynamic LBE, and writes back in place (AA pattern).
+//   k_velocity 1-halo LDS tile: u = sum_i (g_i + K_i) c_i with K_i of the new
+//              pressure, i.e. u = u* - D P / rho.
+//   k_collide  1-halo LDS tile of phi and u: the isotropic central
+//              differences of phi, rho and u, the BGK phase-field collision
+//              and the filter collision of the hydrodynamic LBE, written back
+//              in place (AA pattern).
 //
 // Memory layout (per case): structure of arrays, x fastest; population i of
 // node n at f[i*N + n].  AA pattern: on even steps node x reads slot i of x
@@ -26,6 +27,10 @@
 // The rest population of g is stored as g_0 - P/(rho_ref T): the pressure
 // (kept separately as state) never passes through the distribution storage,
 // and k_moments needs no pressure at all.
+//
+// Addressing: case descriptors and tile tables are read through the
+// constant address space (scalar loads, values in SGPRs); arrays are used
+// through global-address-space pointers with 32-bit node indices.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -53,11 +58,19 @@ struct CaseDev {
     void* J;           // dim*N  scratch: u* = sum g c
     void* S;           // N      scratch: rho_ref T (sum g without the pressure part)
     void* M2;          // 3 (2D) or 6 (3D) * N scratch: sum g c c
-    void* U;           // dim*N  velocity written by a read pass
+    void* U;           // dim*N  velocity u of the current step
     double rho_a, rho_w, tau_a, tau_w, tau_phi, M, W, sigma, lambda_b;
     double grav[3];
     double h_scale, h_inv_scale, g_scale, g_inv_scale, phi_ref;
 };
+
+using CDesc = const PULBM_CST CaseDev;
+
+template <class T> __device__ __forceinline__ PULBM_GLB T* glb(void* p) { return (PULBM_GLB T*)p; }
+
+// A launch covers the tiles of every case in a table of case pointers;
+// tstart[c] is the first tile of case c.
+using CaseTab = CaseDev* const*;
 
 // --------------------------------------------------------------- launch map
 
@@ -66,11 +79,16 @@ struct CaseDev {
 // The grid is a multiple of 8.
 __device__ __forceinline__ int xcd_tile(int bid, int nblocks)
 {
+#ifdef PULBM_NO_XCD_REMAP
+    (void)nblocks;
+    return bid;
+#else
     const int per = nblocks >> 3;
     return (bid & 7) * per + (bid >> 3);
+#endif
 }
 
-__device__ __forceinline__ int find_case(const int* __restrict__ tstart, int ncases, int tile)
+__device__ __forceinline__ int find_case(const PULBM_CST int* tstart, int ncases, int tile)
 {
     int lo = 0, hi = ncases - 1;
     while (lo < hi) {
@@ -82,29 +100,28 @@ __device__ __forceinline__ int find_case(const int* __restrict__ tstart, int nca
 }
 
 struct TileCtx {
-    int ci;          // case index
+    CDesc* cs;
     int ox, oy, oz;  // tile origin
     int64_t step;
     bool active;
 };
 
-// A launch covers the tiles of every case in a table of case pointers;
-// tstart[c] is the first tile of case c.
-using CaseTab = CaseDev* const* __restrict__;
-
 template <class Mo>
-__device__ __forceinline__ TileCtx tile_ctx(CaseTab cases, const int* __restrict__ tstart,
-                                            int ncases, int total_tiles, int step_off)
+__device__ __forceinline__ TileCtx tile_ctx(CaseTab cases, const int* tstart_, int ncases, int total_tiles,
+                                            int step_off)
 {
     TileCtx t;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     t.active = tile < total_tiles;
     if (!t.active) return t;
-    t.ci = find_case(tstart, ncases, tile);
-    const CaseDev& cs = *cases[t.ci];
+    const PULBM_CST int* tstart = (const PULBM_CST int*)tstart_;
+    const int ci = find_case(tstart, ncases, tile);
+    const PULBM_CST uint64_t* tab = (const PULBM_CST uint64_t*)(const void*)cases;
+    t.cs = (CDesc*)(uintptr_t)tab[ci];
+    CDesc& cs = *t.cs;
     t.step = cs.step + step_off;
     t.active = t.step < cs.step_end;
-    int lt = tile - tstart[t.ci];
+    int lt = tile - tstart[ci];
     const int tx = lt % cs.ntx;
     lt /= cs.ntx;
     const int ty = lt % cs.nty;
@@ -115,25 +132,52 @@ __device__ __forceinline__ TileCtx tile_ctx(CaseTab cases, const int* __restrict
     return t;
 }
 
-// Neighbour navigation of one node: linear offsets of a -1/0/+1 step along
-// each axis (periodic wrap included) and which steps leave through a wall.
+// Q slots of N elements of T (structure of arrays).  Addresses are formed as
+// a uniform slot base (SGPRs) plus a 32-bit per-node byte offset, which maps
+// onto the saddr + voffset form of the global memory instructions.
+template <class T>
+struct Slots {
+    PULBM_GLB char* base;
+    uint64_t slot_bytes;  // N * sizeof(T)
+    __device__ __forceinline__ PULBM_GLB T* at(int slot, uint32_t boff) const
+    {
+        return (PULBM_GLB T*)(base + (uint64_t)slot * slot_bytes + boff);
+    }
+};
+
+template <class T> __device__ __forceinline__ Slots<T> slots(void* p, int64_t N)
+{
+    Slots<T> s;
+    s.base = (PULBM_GLB char*)p;
+    s.slot_bytes = (uint64_t)N * sizeof(T);
+    return s;
+}
+
+template <class T> __device__ __forceinline__ PULBM_GLB T* at_node(void* p, uint32_t n)
+{
+    return (PULBM_GLB T*)((PULBM_GLB char*)p + n * (uint32_t)sizeof(T));
+}
+
+// Neighbour navigation of one node: byte offsets (elements of ESZ bytes) of a
+// -1/0/+1 step along each axis (periodic wrap included) and which steps
+// leave through a wall.
 struct Nav {
-    int64_t o[3][3];
+    int o[3][3];
     uint32_t solid;  // bit 2a: the -1 step on axis a is outside a wall; bit 2a+1: the +1 step
 };
 
-__device__ __forceinline__ Nav make_nav(const CaseDev& cs, int x, int y, int z)
+__device__ __forceinline__ Nav make_nav(CDesc& cs, int x, int y, int z, int esz)
 {
     Nav v;
     const int p[3] = {x, y, z};
     const int n[3] = {cs.nx, cs.ny, cs.nz};
-    const int64_t st[3] = {1, (int64_t)cs.nx, (int64_t)cs.nx * cs.ny};
+    const int st[3] = {esz, esz * cs.nx, esz * cs.nx * cs.ny};
     v.solid = 0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         v.o[a][1] = 0;
-        v.o[a][0] = (p[a] == 0) ? (int64_t)(n[a] - 1) * st[a] : -st[a];
-        v.o[a][2] = (p[a] == n[a] - 1) ? -(int64_t)(n[a] - 1) * st[a] : st[a];
+        v.o[a][0] = (p[a] == 0) ? (n[a] - 1) * st[a] : -st[a];
+        v.o[a][2] = (p[a] == n[a] - 1) ? -(n[a] - 1) * st[a] : st[a];
         if (cs.wall[a]) {
             if (p[a] == 0) v.solid |= 1u << (2 * a);
             if (p[a] == n[a] - 1) v.solid |= 1u << (2 * a + 1);
@@ -143,7 +187,7 @@ __device__ __forceinline__ Nav make_nav(const CaseDev& cs, int x, int y, int z)
 }
 
 template <class L>
-__device__ __forceinline__ int64_t nav_off(const Nav& v, int i, int sgn)
+__device__ __forceinline__ int nav_off(const Nav& v, int i, int sgn)
 {
     return v.o[0][sgn * L::c(i, 0) + 1] + v.o[1][sgn * L::c(i, 1) + 1] + v.o[2][sgn * L::c(i, 2) + 1];
 }
@@ -151,33 +195,63 @@ __device__ __forceinline__ int64_t nav_off(const Nav& v, int i, int sgn)
 template <class L>
 __device__ __forceinline__ bool nav_solid(const Nav& v, int i, int sgn)
 {
-    bool s = false;
+    uint32_t m = 0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const int ca = sgn * L::c(i, a);
-        if (ca == -1) s |= (v.solid >> (2 * a)) & 1u;
-        if (ca == 1) s |= (v.solid >> (2 * a + 1)) & 1u;
+        if (ca == -1) m |= 1u << (2 * a);
+        if (ca == 1) m |= 1u << (2 * a + 1);
     }
-    return s;
+    return (v.solid & m) != 0;
 }
 
-// Where the population arriving at node n along direction i is stored.
-template <class L>
-__device__ __forceinline__ int64_t aa_src(const Nav& v, int64_t N, int64_t n, int i, bool odd)
+// Does the tile (or its ghost layer) touch a wall?  Uniform per block; tiles
+// that do not skip every bounce-back test.
+template <class Mo>
+__device__ __forceinline__ bool tile_at_wall(CDesc& cs, int ox, int oy, int oz)
 {
-    if (!odd) return (int64_t)i * N + n;
-    if (nav_solid<L>(v, i, -1)) return (int64_t)i * N + n;  // reflected at the wall last step
-    return (int64_t)opp(i) * N + n + nav_off<L>(v, i, -1);
+    return (cs.wall[0] && (ox == 0 || ox + Mo::TX >= cs.nx)) || (cs.wall[1] && (oy == 0 || oy + Mo::TY >= cs.ny)) ||
+           (cs.wall[2] && (oz == 0 || oz + Mo::TZ >= cs.nz));
 }
 
-// Where node n writes its post-collision population i; *bb tells whether it
-// is reflected by a wall (and needs the force correction for g).
-template <class L>
-__device__ __forceinline__ int64_t aa_dst(const Nav& v, int64_t N, int64_t n, int i, bool odd, bool* bb)
+// Population loads and stores.  The populations of a step are read once and
+// written once and the state is far larger than the caches, so they can be
+// marked non-temporal.
+template <class S> __device__ __forceinline__ S pop_ld(const PULBM_GLB S* p)
 {
-    *bb = nav_solid<L>(v, i, +1);
-    if (!odd || *bb) return (int64_t)opp(i) * N + n;
-    return (int64_t)i * N + n + nav_off<L>(v, i, +1);
+#ifdef PULBM_NT_LOAD
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
+template <class S> __device__ __forceinline__ void pop_st(PULBM_GLB S* p, S v)
+{
+#ifdef PULBM_NT_STORE
+    __builtin_nontemporal_store(v, p);
+#else
+    *p = v;
+#endif
+}
+
+// Population arriving at the node (byte offset nb) along direction i.
+template <class L, bool WALL, class S>
+__device__ __forceinline__ S aa_load(const Slots<S>& f, uint32_t nb, const Nav& v, int i, bool odd)
+{
+    if (!odd) return pop_ld(f.at(i, nb));
+    if (WALL && nav_solid<L>(v, i, -1)) return pop_ld(f.at(i, nb));  // reflected at a wall last step
+    return pop_ld(f.at(opp(i), nb + (uint32_t)nav_off<L>(v, i, -1)));
+}
+
+// Store the node's post-collision population i where it streams to; a
+// population leaving through a wall goes to the slot the node reads back as
+// the reflected direction.
+template <class L, bool WALL, class S>
+__device__ __forceinline__ void aa_store(const Slots<S>& f, uint32_t nb, const Nav& v, int i, bool odd, S val,
+                                         bool bb)
+{
+    if (!odd || (WALL && bb)) pop_st(f.at(opp(i), nb), val);
+    else pop_st(f.at(i, nb + (uint32_t)nav_off<L>(v, i, +1)), val);
 }
 
 // ---------------------------------------------------------- tile regions
@@ -204,7 +278,29 @@ struct Region {
     __device__ static __forceinline__ int idx(int ix, int iy, int iz) { return ix + RX * (iy + RY * iz); }
 };
 
+// 1-halo region of a tile: cell k -> mirror node index, wall offsets, crossings.
+template <class Mo, int DIMV>
+struct Halo1 {
+    static constexpr int ZH = DIMV == 3 ? 1 : 0;
+    static constexpr int RX = Mo::TX + 2, RY = Mo::TY + 2, RZ = Mo::TZ + 2 * ZH;
+    using R = Region<RX, RY, RZ>;
+    __device__ static __forceinline__ uint32_t cell(CDesc& cs, const TileCtx& t, int k, int off[3], int* cr)
+    {
+        const int ix = k % RX, iy = (k / RX) % RY, iz = k / (RX * RY);
+        *cr = 0;
+        const int mx = resolve_axis(t.ox - 1 + ix, cs.nx, cs.wall[0], &off[0], cr);
+        const int my = resolve_axis(t.oy - 1 + iy, cs.ny, cs.wall[1], &off[1], cr);
+        const int mz = resolve_axis(t.oz - ZH + iz, cs.nz, cs.wall[2], &off[2], cr);
+        return (uint32_t)mx + (uint32_t)cs.nx * ((uint32_t)my + (uint32_t)cs.ny * (uint32_t)mz);
+    }
+};
+
 // ------------------------------------------------------------ physics
+
+template <class CT> __device__ __forceinline__ CT rcp(CT x) { return (CT)1 / x; }
+template <> __device__ __forceinline__ float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <class CT> __device__ __forceinline__ CT sqrt_(CT x) { return sqrt(x); }
+template <> __device__ __forceinline__ float sqrt_<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 template <class CT>
 struct Phys {
@@ -214,12 +310,11 @@ struct Phys {
     CT sigW15;   // 3 sigma W / 2
     CT lambda_b;
     CT grav[3];
-    CT inv_rho_a_T;
     int delta_theta;
 };
 
 template <class CT>
-__device__ __forceinline__ Phys<CT> make_phys(const CaseDev& cs)
+__device__ __forceinline__ Phys<CT> make_phys(CDesc& cs)
 {
     Phys<CT> p;
     p.rho_a = (CT)cs.rho_a;
@@ -234,7 +329,6 @@ __device__ __forceinline__ Phys<CT> make_phys(const CaseDev& cs)
     p.grav[0] = (CT)cs.grav[0];
     p.grav[1] = (CT)cs.grav[1];
     p.grav[2] = (CT)cs.grav[2];
-    p.inv_rho_a_T = (CT)(1.0 / (cs.rho_a * kT));
     p.delta_theta = cs.delta_theta;
     return p;
 }
@@ -247,142 +341,211 @@ struct NodeVals {
     CT phi, u[3], gphi[3], lphi, grho[3], G[3][3];  // G[a][b] = d u_a / d x_b
 };
 
-// Equilibria of both lattices at one node, then (unless INIT) the collisions.
-//   h[j]  in: post-streaming h_j; out: post-collision h*_j (INIT: h^eq_j)
-//   g[i]  out: post-collision g*_i (INIT: g^eq_i); the rest entry excludes
-//         the P / (rho_ref T) part
-//   M2    sum g c c of the post-streaming populations (unused with INIT)
-//   F     total force (for the wall correction); rho of the node
-template <int DIMV, bool INIT, class CT>
-__device__ __forceinline__ void node_physics(const Phys<CT>& p, const NodeVals<CT>& v,
-                                             CT* __restrict__ h, const CT* __restrict__ M2,
-                                             CT* __restrict__ g, CT F[3], CT* rho_out)
-{
-    using Mo = Model<DIMV>;
-    using G = typename Mo::G;
-    using H = typename Mo::H;
-    constexpr int D = DIMV;
-    const CT T = (CT)kT, iT = (CT)3.0, i2T2 = (CT)4.5, i2T = (CT)1.5;
-    const CT eps = (CT)1.0e-10;
-    const CT phi = v.phi;
+// Macroscopic part of the collision of one node (everything but the
+// per-direction loops): phase-field theta and normal, hydrodynamic force,
+// first moment of g^eq, B div u and the non-equilibrium momentum flux Pi.
+template <int DIMV, class CT>
+struct NodeCoef {
+    CT theta, nv[3];     // phase field
+    CT base_h;           // 1 - u^2 / (2T)
+    CT rho, F[3];        // for the wall correction
+    CT av[3];            // u + F / rho + sigma . grad rho / rho^2
+    CT gbase;            // B div / T - u^2 / (2T)
+    CT Bdiv;
+    CT kPi[3][3], kTr;   // (1 - 1/tau) / (2 T^2) * Pi, and * T tr(Pi)
+};
 
-    // ---- phase field: normal, theta (+ delta theta), Gamma, h^eq, BGK
+template <int DIMV, bool INIT, class CT>
+__device__ __forceinline__ NodeCoef<DIMV, CT> node_coef(const Phys<CT>& p, const NodeVals<CT>& v,
+                                                        const CT* __restrict__ M2)
+{
+    constexpr int D = DIMV;
+    const CT T = (CT)kT, i2T2 = (CT)4.5, i2T = (CT)1.5, iT = (CT)3.0;
+    const CT eps = (CT)1.0e-10;
+    NodeCoef<DIMV, CT> k;
+    const CT phi = v.phi;
+    // phase field: normal, theta (+ delta theta)
     CT gn2 = 0;
 #pragma unroll
     for (int a = 0; a < D; ++a) gn2 += v.gphi[a] * v.gphi[a];
-    const CT gn = sqrt(gn2);
-    const CT inv_n = (CT)1 / (gn + eps);
-    CT nv[3] = {0, 0, 0};
+    const CT gn = sqrt_(gn2);
+    const CT inv_n = rcp(gn + eps);
 #pragma unroll
-    for (int a = 0; a < D; ++a) nv[a] = v.gphi[a] * inv_n;
+    for (int a = 0; a < 3; ++a) k.nv[a] = a < D ? v.gphi[a] * inv_n : (CT)0;
     const CT dphi = phi - (CT)0.5;
     CT theta = p.theta0 * ((CT)1 - (CT)4 * dphi * dphi);
     if (p.delta_theta) {
-        const CT s = v.lphi / (fabs(v.lphi) + eps);
+        const CT s = v.lphi * rcp(fabs(v.lphi) + eps);
         const CT iD = (CT)1.0e4;
         const CT Y1 = fmin(clamp01((phi - (CT)0.8) * iD), clamp01(-(phi - (CT)1) * iD));
         const CT Y2 = fmin(clamp01(phi * iD), clamp01(-(phi - (CT)0.2) * iD));
         theta += (CT)(-22.5) * p.theta0 * gn * (((CT)1 + s) * Y1 + ((CT)1 - s) * Y2);
     }
+    k.theta = theta;
     CT u2 = 0;
 #pragma unroll
     for (int a = 0; a < D; ++a) u2 += v.u[a] * v.u[a];
-    const CT base = (CT)1 - u2 * i2T;
-#pragma unroll
-    for (int j = 0; j < H::Q; ++j) {
-        CT cu = 0, cn = 0;
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-            if (H::c(j, a) == 1) { cu += v.u[a]; cn += nv[a]; }
-            if (H::c(j, a) == -1) { cu -= v.u[a]; cn -= nv[a]; }
-        }
-        const CT wj = (CT)H::w(j);
-        const CT gam = wj * (base + cu * iT + cu * cu * i2T2);
-        const CT heq = phi * gam + theta * wj * cn;
-        if (INIT) h[j] = heq;
-        else h[j] = h[j] + (heq - h[j]) * p.inv_tau_phi;
-    }
-
-    // ---- hydrodynamics: rho, tau, nu, mu, F, sigma, B, g^eq, filter
+    k.base_h = (CT)1 - u2 * i2T;
+    // hydrodynamics
     const CT pc = clamp01(phi);
     const CT rho = p.rho_a + pc * p.drho;
     const CT tau = p.tau_a + pc * p.dtau;
     const CT nu = T * (tau - (CT)0.5);
     const CT mu = p.sig48W * phi * (phi - (CT)1) * dphi - p.sigW15 * v.lphi;
-    const CT irho = (CT)1 / rho;
+    const CT irho = rcp(rho);
+    k.rho = rho;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) F[a] = 0;
-#pragma unroll
-    for (int a = 0; a < D; ++a) F[a] = rho * p.grav[a] + mu * v.gphi[a];
+    for (int a = 0; a < 3; ++a) k.F[a] = a < D ? rho * p.grav[a] + mu * v.gphi[a] : (CT)0;
     CT div = 0;
 #pragma unroll
     for (int a = 0; a < D; ++a) div += v.G[a][a];
     const CT bulk = rho * (CT)(2.0 / 3.0) * (p.lambda_b - nu) * div;
-    // a = u + F / rho + sigma . grad rho / rho^2 : first moment of g^eq
-    CT av[3] = {0, 0, 0};
+    const CT rnu = rho * nu;
 #pragma unroll
-    for (int l = 0; l < D; ++l) {
+    for (int l = 0; l < 3; ++l) {
+        if (l >= D) { k.av[l] = 0; continue; }
         CT sg = 0;
 #pragma unroll
         for (int m = 0; m < D; ++m) {
-            CT s_lm = rho * nu * (v.G[l][m] + v.G[m][l]);
+            CT s_lm = rnu * (v.G[l][m] + v.G[m][l]);
             if (l == m) s_lm += bulk;
             sg += s_lm * v.grho[m];
         }
-        av[l] = v.u[l] + F[l] * irho + sg * irho * irho;
+        k.av[l] = v.u[l] + (k.F[l] + sg * irho) * irho;
     }
     const CT B = (CT)(2.0 / 3.0) * (nu - p.lambda_b) + T * (CT)0.5;
-    const CT Bdiv = B * div;
-    // Pi = sum c c (g - g^eq) = M2 - (u u + B div I) on these lattices
-    CT Pi[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    CT kf = 0, trPi = 0;
+    k.Bdiv = B * div;
+    k.gbase = k.Bdiv * iT - u2 * i2T;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) k.kPi[a][b] = 0;
+    k.kTr = 0;
     if (!INIT) {
+        // Pi = sum c c (g - g^eq) = M2 - (u u + B div I) on these lattices
+        CT Pi[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
         if (D == 2) {
-            Pi[0][0] = M2[0] - v.u[0] * v.u[0] - Bdiv;
-            Pi[1][1] = M2[1] - v.u[1] * v.u[1] - Bdiv;
+            Pi[0][0] = M2[0] - v.u[0] * v.u[0] - k.Bdiv;
+            Pi[1][1] = M2[1] - v.u[1] * v.u[1] - k.Bdiv;
             Pi[0][1] = Pi[1][0] = M2[2] - v.u[0] * v.u[1];
         } else {
-            Pi[0][0] = M2[0] - v.u[0] * v.u[0] - Bdiv;
-            Pi[1][1] = M2[1] - v.u[1] * v.u[1] - Bdiv;
-            Pi[2][2] = M2[2] - v.u[2] * v.u[2] - Bdiv;
+            Pi[0][0] = M2[0] - v.u[0] * v.u[0] - k.Bdiv;
+            Pi[1][1] = M2[1] - v.u[1] * v.u[1] - k.Bdiv;
+            Pi[2][2] = M2[2] - v.u[2] * v.u[2] - k.Bdiv;
             Pi[0][1] = Pi[1][0] = M2[3] - v.u[0] * v.u[1];
             Pi[0][2] = Pi[2][0] = M2[4] - v.u[0] * v.u[2];
             Pi[1][2] = Pi[2][1] = M2[5] - v.u[1] * v.u[2];
         }
+        const CT kf = ((CT)1 - rcp(tau)) * i2T2;
+        CT tr = 0;
 #pragma unroll
-        for (int a = 0; a < D; ++a) trPi += Pi[a][a];
-        kf = ((CT)1 - (CT)1 / tau) * i2T2;
+        for (int a = 0; a < D; ++a) tr += Pi[a][a];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) k.kPi[a][b] = kf * Pi[a][b];
+        k.kTr = kf * T * tr;
     }
-    const CT gbase = Bdiv * iT - u2 * i2T;
-#pragma unroll
-    for (int i = 0; i < G::Q; ++i) {
-        const CT wi = (CT)G::w(i);
-        CT ca = 0, cu = 0;
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-            if (G::c(i, a) == 1) { ca += av[a]; cu += v.u[a]; }
-            if (G::c(i, a) == -1) { ca -= av[a]; cu -= v.u[a]; }
-        }
-        CT geq = wi * (ca * iT + cu * cu * i2T2 + gbase);
-        if (i == 0) geq -= Bdiv * iT;
-        if (!INIT) {
-            CT cPc = 0;
-#pragma unroll
-            for (int a = 0; a < D; ++a)
-#pragma unroll
-                for (int b = 0; b < D; ++b) {
-                    const int cc = G::c(i, a) * G::c(i, b);
-                    if (cc == 1) cPc += Pi[a][b];
-                    if (cc == -1) cPc -= Pi[a][b];
-                }
-            geq += wi * kf * (cPc - T * trPi);
-        }
-        g[i] = geq;
-    }
-    *rho_out = rho;
+    return k;
 }
 
-// Isotropic central differences (Sec. II) of a tile field at cell c0:
+// h^eq_j (INIT) or the BGK post-collision h*_j from the incoming h_j.
+template <class H, int D, bool INIT, class CT>
+__device__ __forceinline__ CT h_out(const Phys<CT>& p, const NodeVals<CT>& v, const NodeCoef<D, CT>& k, int j,
+                                    CT hj)
+{
+    CT cu = 0, cn = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        if (H::c(j, a) == 1) { cu += v.u[a]; cn += k.nv[a]; }
+        if (H::c(j, a) == -1) { cu -= v.u[a]; cn -= k.nv[a]; }
+    }
+    const CT wj = (CT)H::w(j);
+    const CT heq = wj * (v.phi * (k.base_h + cu * (CT)3.0 + cu * cu * (CT)4.5) + k.theta * cn);
+    return INIT ? heq : hj + (heq - hj) * p.inv_tau_phi;
+}
+
+// g^eq_i (INIT) or the filtered post-collision g*_i; the rest entry excludes
+// the P / (rho_ref T) part.
+template <class G, int D, bool INIT, class CT>
+__device__ __forceinline__ CT g_out(const NodeVals<CT>& v, const NodeCoef<D, CT>& k, int i)
+{
+    const CT wi = (CT)G::w(i);
+    CT ca = 0, cu = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        if (G::c(i, a) == 1) { ca += k.av[a]; cu += v.u[a]; }
+        if (G::c(i, a) == -1) { ca -= k.av[a]; cu -= v.u[a]; }
+    }
+    CT inner = ca * (CT)3.0 + cu * cu * (CT)4.5 + k.gbase;
+    if (!INIT) {
+        CT cPc = 0;
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int b = 0; b < D; ++b) {
+                const int cc = G::c(i, a) * G::c(i, b);
+                if (cc == 1) cPc += k.kPi[a][b];
+                if (cc == -1) cPc -= k.kPi[a][b];
+            }
+        inner += cPc - k.kTr;
+    }
+    CT geq = wi * inner;
+    if (i == 0) geq -= k.Bdiv * (CT)3.0;
+    return geq;
+}
+
+// Opposite directions i and i+1 (i odd) have c_{i+1} = -c_i: the terms odd in
+// c change sign and the even ones do not, so each pair shares one evaluation.
+// h^eq (INIT) or the BGK post-collision h* for the pair (j, j+1).
+template <class H, int D, bool INIT, class CT>
+__device__ __forceinline__ void h_pair(const Phys<CT>& p, const NodeVals<CT>& v, const NodeCoef<D, CT>& k,
+                                       int j, CT hj, CT hk, CT* oj, CT* ok)
+{
+    CT cu = 0, cn = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        if (H::c(j, a) == 1) { cu += v.u[a]; cn += k.nv[a]; }
+        if (H::c(j, a) == -1) { cu -= v.u[a]; cn -= k.nv[a]; }
+    }
+    const CT wj = (CT)H::w(j);
+    const CT even = wj * v.phi * (k.base_h + cu * cu * (CT)4.5);
+    const CT odd = wj * (v.phi * cu * (CT)3.0 + k.theta * cn);
+    const CT ej = even + odd, ek = even - odd;
+    *oj = INIT ? ej : hj + (ej - hj) * p.inv_tau_phi;
+    *ok = INIT ? ek : hk + (ek - hk) * p.inv_tau_phi;
+}
+
+// g^eq (INIT) or the filtered post-collision g* for the pair (i, i+1).
+template <class G, int D, bool INIT, class CT>
+__device__ __forceinline__ void g_pair(const NodeVals<CT>& v, const NodeCoef<D, CT>& k, int i, CT* oi, CT* ok)
+{
+    const CT wi = (CT)G::w(i);
+    CT ca = 0, cu = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        if (G::c(i, a) == 1) { ca += k.av[a]; cu += v.u[a]; }
+        if (G::c(i, a) == -1) { ca -= k.av[a]; cu -= v.u[a]; }
+    }
+    CT even = cu * cu * (CT)4.5 + k.gbase;
+    if (!INIT) {
+        CT cPc = 0;
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int b = 0; b < D; ++b) {
+                const int cc = G::c(i, a) * G::c(i, b);
+                if (cc == 1) cPc += k.kPi[a][b];
+                if (cc == -1) cPc -= k.kPi[a][b];
+            }
+        even += cPc - k.kTr;
+    }
+    const CT odd = ca * (CT)3.0;
+    *oi = wi * (even + odd);
+    *ok = wi * (even - odd);
+}
+
+// Isotropic central differences (Sec. II) of a tile field at cell (cx,cy,cz):
 // grad_a q = sum_i w_i c_ia (q(+c_i) - q(-c_i)) / (2T), lap q = 2 sum_i w_i (q(+c_i) - q0) / T.
 template <class G, class RG, class CT, class F>
 __device__ __forceinline__ void stencil(F q, int cx, int cy, int cz, CT grad[3], CT* lap)
@@ -407,41 +570,45 @@ __device__ __forceinline__ void stencil(F q, int cx, int cy, int cz, CT grad[3],
     if (lap) *lap = l * (CT)6.0;                             // 2/T
 }
 
+// Keeps the scheduler from hoisting the loads of a later phase into an
+// earlier one (which would hold their registers across both).
+#ifndef PULBM_NO_PHASE_FENCE
+#define PULBM_PHASE_FENCE() __builtin_amdgcn_sched_barrier(0)
+#else
+#define PULBM_PHASE_FENCE() ((void)0)
+#endif
+
+template <class Mo>
+__device__ __forceinline__ void local_xyz(int* lx, int* ly, int* lz)
+{
+    *lx = threadIdx.x % Mo::TX;
+    *ly = (threadIdx.x / Mo::TX) % Mo::TY;
+    *lz = threadIdx.x / (Mo::TX * Mo::TY);
+}
+
 // ================================================================ kernels
 
 // --- moments: phi, u* = sum g c, S, M2 (per node; no halo)
-template <int DIMV, class S>
-__global__ __launch_bounds__(256) void k_moments(CaseTab cases, const int* __restrict__ tstart,
-                                                 int ncases, int total_tiles, int step_off)
+template <int DIMV, class S, bool WALL>
+__device__ __forceinline__ void moments_node(CDesc& cs, int x, int y, int z, bool odd)
 {
     using Mo = Model<DIMV>;
     using G = typename Mo::G;
     using H = typename Mo::H;
     using CT = typename Codec<S>::CT;
-    const TileCtx t = tile_ctx<Mo>(cases, tstart, ncases, total_tiles, step_off);
-    if (!t.active) return;
-    const CaseDev& cs = *cases[t.ci];
-    const int lx = threadIdx.x % Mo::TX, ly = (threadIdx.x / Mo::TX) % Mo::TY,
-              lz = threadIdx.x / (Mo::TX * Mo::TY);
-    const int x = t.ox + lx, y = t.oy + ly, z = t.oz + lz;
-    if (x >= cs.nx || y >= cs.ny || z >= cs.nz) return;
-    const int64_t N = cs.N;
-    const int64_t n = x + (int64_t)cs.nx * (y + (int64_t)cs.ny * z);
-    const bool odd = t.step & 1;
-    const Nav nv = make_nav(cs, x, y, z);
-    const S* __restrict__ hp = (const S*)cs.h;
-    const S* __restrict__ gp = (const S*)cs.g;
+    const uint32_t n = (uint32_t)x + (uint32_t)cs.nx * ((uint32_t)y + (uint32_t)cs.ny * (uint32_t)z);
+    const uint32_t nb = n * (uint32_t)sizeof(S);
+    const Nav nv = make_nav(cs, x, y, z, (int)sizeof(S));
+    const Slots<S> hs = slots<S>(cs.h, cs.N), gs = slots<S>(cs.g, cs.N);
     const CT hsc = (CT)cs.h_inv_scale, gsc = (CT)cs.g_inv_scale;
     const CT phr = (CT)cs.phi_ref;
-
     CT phi = 0;
 #pragma unroll
-    for (int j = 0; j < H::Q; ++j)
-        phi += Codec<S>::load(hp, aa_src<H>(nv, N, n, j, odd), hsc, phr * (CT)H::w(j));
+    for (int j = 0; j < H::Q; ++j) phi += Codec<S>::dec(aa_load<H, WALL>(hs, nb, nv, j, odd), hsc, phr * (CT)H::w(j));
     CT sum = 0, J[3] = {0, 0, 0}, m2[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
     for (int i = 0; i < G::Q; ++i) {
-        const CT f = Codec<S>::load(gp, aa_src<G>(nv, N, n, i, odd), gsc, (CT)0);
+        const CT f = Codec<S>::dec(aa_load<G, WALL>(gs, nb, nv, i, odd), gsc, (CT)0);
         sum += f;
 #pragma unroll
         for (int a = 0; a < DIMV; ++a) {
@@ -464,75 +631,84 @@ __global__ __launch_bounds__(256) void k_moments(CaseTab cases, const int* __res
             }
         }
     }
-    CT* phiv = (CT*)cs.phi;
-    CT* Jv = (CT*)cs.J;
-    CT* Sv = (CT*)cs.S;
-    CT* M2v = (CT*)cs.M2;
-    phiv[n] = phi;
+    const uint32_t na = n * (uint32_t)sizeof(CT);
+    *at_node<CT>(cs.phi, n) = phi;
+    const Slots<CT> Js = slots<CT>(cs.J, cs.N), Ms = slots<CT>(cs.M2, cs.N);
 #pragma unroll
-    for (int a = 0; a < DIMV; ++a) Jv[a * N + n] = J[a];
-    Sv[n] = (CT)(cs.rho_a * kT) * sum;
+    for (int a = 0; a < DIMV; ++a) *Js.at(a, na) = J[a];
+    *at_node<CT>(cs.S, n) = (CT)(cs.rho_a * kT) * sum;
     constexpr int NM = DIMV == 2 ? 3 : 6;
 #pragma unroll
-    for (int k = 0; k < NM; ++k) M2v[k * N + n] = m2[k];
+    for (int k = 0; k < NM; ++k) *Ms.at(k, na) = m2[k];
+}
+
+template <int DIMV, class S>
+__global__ __launch_bounds__(256) void k_moments(CaseTab cases, const int* tstart, int ncases, int total_tiles,
+                                                 int step_off)
+{
+    using Mo = Model<DIMV>;
+    const TileCtx t = tile_ctx<Mo>(cases, tstart, ncases, total_tiles, step_off);
+    if (!t.active) return;
+    CDesc& cs = *t.cs;
+    int lx, ly, lz;
+    local_xyz<Mo>(&lx, &ly, &lz);
+    const int x = t.ox + lx, y = t.oy + ly, z = t.oz + lz;
+    if (x >= cs.nx || y >= cs.ny || z >= cs.nz) return;
+    const bool odd = t.step & 1;
+    if (tile_at_wall<Mo>(cs, t.ox, t.oy, t.oz)) moments_node<DIMV, S, true>(cs, x, y, z, odd);
+    else moments_node<DIMV, S, false>(cs, x, y, z, odd);
 }
 
 // --- pressure (Sec. II): P = rho_ref T sum_i (g_i + (1 + omega) K_i)
 //     + omega rho_ref sum_i w_i c_i . u*(x - c_i), K_i from the previous
-//     pressure.  FP64 arithmetic whatever the storage precision.
-template <int DIMV, class AT>
-__global__ __launch_bounds__(256) void k_pressure(CaseTab cases, const int* __restrict__ tstart,
-                                                  int ncases, int total_tiles, int step_off)
+//     pressure.  FP64 arithmetic whatever the storage precision (values are
+//     widened once, when the tile is staged in LDS).
+template <int DIMV, class AT, bool WALL, class R>
+__device__ __forceinline__ void pressure_tile(CDesc& cs, const TileCtx& t, double* sP, double* sGD,
+                                              double (*sJ)[R::N])
 {
     using Mo = Model<DIMV>;
     using G = typename Mo::G;
-    constexpr int ZH = DIMV == 3 ? 1 : 0;
-    constexpr int RX = Mo::TX + 2, RY = Mo::TY + 2, RZ = Mo::TZ + 2 * ZH;
-    using R = Region<RX, RY, RZ>;
-    __shared__ double sP[R::N], sGD[R::N], sJ[DIMV][R::N];
-    const TileCtx t = tile_ctx<Mo>(cases, tstart, ncases, total_tiles, step_off);
-    if (!t.active) return;
-    const CaseDev& cs = *cases[t.ci];
-    const int64_t N = cs.N;
-    const AT* __restrict__ Pl = (const AT*)cs.P[t.step & 1];
-    AT* __restrict__ Pn = (AT*)cs.P[(t.step + 1) & 1];
-    const AT* __restrict__ Jv = (const AT*)cs.J;
-    for (int k = threadIdx.x; k < R::N; k += 256) {
-        const int ix = k % RX, iy = (k / RX) % RY, iz = k / (RX * RY);
-        int off[3], cr = 0;
-        const int mx = resolve_axis(t.ox - 1 + ix, cs.nx, cs.wall[0], &off[0], &cr);
-        const int my = resolve_axis(t.oy - 1 + iy, cs.ny, cs.wall[1], &off[1], &cr);
-        const int mz = resolve_axis(t.oz - ZH + iz, cs.nz, cs.wall[2], &off[2], &cr);
-        const int64_t m = mx + (int64_t)cs.nx * (my + (int64_t)cs.ny * mz);
-        sP[k] = (double)Pl[m];
+    using HR = Halo1<Mo, DIMV>;
+    void* Pl = cs.P[t.step & 1];
+    const Slots<AT> Js = slots<AT>(cs.J, cs.N);
+    // fixed trip count, fully unrolled: every halo load is issued before the
+    // first LDS write waits on one
+#pragma unroll
+    for (int it = 0; it < (R::N + 255) / 256; ++it) {
+        const int k = threadIdx.x + 256 * it;
+        if (k >= R::N) break;
+        int off[3], cr;
+        const uint32_t m = HR::cell(cs, t, k, off, &cr);
+        sP[k] = (double)*at_node<AT>(Pl, m);
         // ghost pressure = P(mirror) + rho(x) g.(ghost - mirror): keep g.off
-        sGD[k] = cs.grav[0] * off[0] + cs.grav[1] * off[1] + cs.grav[2] * off[2];
+        if (WALL) sGD[k] = cs.grav[0] * off[0] + cs.grav[1] * off[1] + cs.grav[2] * off[2];
 #pragma unroll
         for (int a = 0; a < DIMV; ++a) {
-            double j = (double)Jv[a * N + m];
+            double j = (double)*Js.at(a, m * (uint32_t)sizeof(AT));
             // u* at a ghost: flow part odd, body-force part even
-            if (cr & 1) j = -j + 2.0 * cs.grav[a];
+            if (WALL && (cr & 1)) j = -j + 2.0 * cs.grav[a];
             sJ[a][k] = j;
         }
     }
     __syncthreads();
-    const int lx = threadIdx.x % Mo::TX, ly = (threadIdx.x / Mo::TX) % Mo::TY,
-              lz = threadIdx.x / (Mo::TX * Mo::TY);
+    int lx, ly, lz;
+    local_xyz<Mo>(&lx, &ly, &lz);
     const int x = t.ox + lx, y = t.oy + ly, z = t.oz + lz;
     if (x >= cs.nx || y >= cs.ny || z >= cs.nz) return;
-    const int64_t n = x + (int64_t)cs.nx * (y + (int64_t)cs.ny * z);
-    const double phi = (double)((const AT*)cs.phi)[n];
+    const uint32_t n = (uint32_t)x + (uint32_t)cs.nx * ((uint32_t)y + (uint32_t)cs.ny * (uint32_t)z);
+    const double phi = (double)*at_node<AT>(cs.phi, n);
     const double ra = cs.rho_a, rw = cs.rho_w;
     const double pc = phi < 0.0 ? 0.0 : (phi > 1.0 ? 1.0 : phi);
     const double rho = ra + pc * (rw - ra);
     const double omega = (rho - ra) / (rw - ra) * (rw / ra - 1.0);
-    const int cx = lx + 1, cy = ly + 1, cz = lz + ZH;
+    const int cx = lx + 1, cy = ly + 1, cz = lz + HR::ZH;
     const double P0 = sP[R::idx(cx, cy, cz)];
     double sk = 0.0, su = 0.0;
 #pragma unroll
     for (int i = 1; i < G::Q; ++i) {
         const int k = R::idx(cx - G::c(i, 0), cy - G::c(i, 1), cz - G::c(i, 2));
-        sk += G::w(i) * (sP[k] + rho * sGD[k] - P0);
+        sk += G::w(i) * ((WALL ? sP[k] + rho * sGD[k] : sP[k]) - P0);
         double cu = 0.0;
 #pragma unroll
         for (int a = 0; a < DIMV; ++a) {
@@ -542,240 +718,291 @@ __global__ __launch_bounds__(256) void k_pressure(CaseTab cases, const int* __re
         su += G::w(i) * cu;
     }
     // rho_ref T (1 + omega) K summed = (1 + omega) rho_ref / rho * sum w (dP)
-    const double P = P0 + (double)((const AT*)cs.S)[n] + (1.0 + omega) * ra / rho * sk +
-                     omega * ra * su;
-    Pn[n] = (AT)P;
+    const double P = P0 + (double)*at_node<AT>(cs.S, n) + (1.0 + omega) * ra / rho * sk + omega * ra * su;
+    *at_node<AT>(cs.P[(t.step + 1) & 1], n) = (AT)P;
 }
 
-// --- collide + stream.  READ: stop after rebuilding u (read pass).
-template <int DIMV, class S, bool READ>
-__global__ __launch_bounds__(256) void k_collide(CaseTab cases, const int* __restrict__ tstart,
-                                                 int ncases, int total_tiles, int step_off)
+template <int DIMV, class AT>
+__global__ __launch_bounds__(256) void k_pressure(CaseTab cases, const int* tstart, int ncases,
+                                                  int total_tiles, int step_off)
+{
+    using Mo = Model<DIMV>;
+    using R = typename Halo1<Mo, DIMV>::R;
+    __shared__ double sP[R::N], sGD[R::N], sJ[DIMV][R::N];
+    const TileCtx t = tile_ctx<Mo>(cases, tstart, ncases, total_tiles, step_off);
+    if (!t.active) return;
+    CDesc& cs = *t.cs;
+    if (tile_at_wall<Mo>(cs, t.ox, t.oy, t.oz)) pressure_tile<DIMV, AT, true, R>(cs, t, sP, sGD, sJ);
+    else pressure_tile<DIMV, AT, false, R>(cs, t, sP, sGD, sJ);
+}
+
+// --- velocity: u = u* + sum_i K_i c_i with K_i of the new pressure.
+template <int DIMV, class CT, bool WALL, class R>
+__device__ __forceinline__ void velocity_tile(CDesc& cs, const TileCtx& t, CT* sP, CT* sGD)
 {
     using Mo = Model<DIMV>;
     using G = typename Mo::G;
-    using H = typename Mo::H;
-    using CT = typename Codec<S>::CT;
-    constexpr int ZH = DIMV == 3 ? 1 : 0;
-    constexpr int R1X = Mo::TX + 2, R1Y = Mo::TY + 2, R1Z = Mo::TZ + 2 * ZH;
-    constexpr int R2X = Mo::TX + 4, R2Y = Mo::TY + 4, R2Z = Mo::TZ + 4 * ZH;
-    using R1 = Region<R1X, R1Y, R1Z>;
-    using R2 = Region<R2X, R2Y, R2Z>;
-    __shared__ CT sP[R2::N], sGD[R2::N], sPhi[R1::N], sU[DIMV][R1::N];
-    const TileCtx t = tile_ctx<Mo>(cases, tstart, ncases, total_tiles, step_off);
-    if (!t.active) return;
-    const CaseDev& cs = *cases[t.ci];
-    const int64_t N = cs.N;
-    const CT* __restrict__ Pn = (const CT*)cs.P[(t.step + 1) & 1];
-    const CT* __restrict__ phiv = (const CT*)cs.phi;
-    const CT* __restrict__ Jv = (const CT*)cs.J;
-    const Phys<CT> ph = make_phys<CT>(cs);
-
-    // A: new pressure on the 2-halo region, phi and u* on the 1-halo region
-    for (int k = threadIdx.x; k < R2::N; k += 256) {
-        const int ix = k % R2X, iy = (k / R2X) % R2Y, iz = k / (R2X * R2Y);
-        int off[3], cr = 0;
-        const int mx = resolve_axis(t.ox - 2 + ix, cs.nx, cs.wall[0], &off[0], &cr);
-        const int my = resolve_axis(t.oy - 2 + iy, cs.ny, cs.wall[1], &off[1], &cr);
-        const int mz = resolve_axis(t.oz - 2 * ZH + iz, cs.nz, cs.wall[2], &off[2], &cr);
-        const int64_t m = mx + (int64_t)cs.nx * (my + (int64_t)cs.ny * mz);
-        sP[k] = Pn[m];
-        sGD[k] = (CT)(cs.grav[0] * off[0] + cs.grav[1] * off[1] + cs.grav[2] * off[2]);
-    }
-    for (int k = threadIdx.x; k < R1::N; k += 256) {
-        const int ix = k % R1X, iy = (k / R1X) % R1Y, iz = k / (R1X * R1Y);
-        int off[3], cr = 0;
-        const int mx = resolve_axis(t.ox - 1 + ix, cs.nx, cs.wall[0], &off[0], &cr);
-        const int my = resolve_axis(t.oy - 1 + iy, cs.ny, cs.wall[1], &off[1], &cr);
-        const int mz = resolve_axis(t.oz - ZH + iz, cs.nz, cs.wall[2], &off[2], &cr);
-        const int64_t m = mx + (int64_t)cs.nx * (my + (int64_t)cs.ny * mz);
-        sPhi[k] = phiv[m];
+    using HR = Halo1<Mo, DIMV>;
+    void* Pn = cs.P[(t.step + 1) & 1];
+    // fixed trip count, fully unrolled: every halo load is issued before the
+    // first LDS write waits on one
 #pragma unroll
-        for (int a = 0; a < DIMV; ++a) sU[a][k] = Jv[a * N + m];
+    for (int it = 0; it < (R::N + 255) / 256; ++it) {
+        const int k = threadIdx.x + 256 * it;
+        if (k >= R::N) break;
+        int off[3], cr;
+        const uint32_t m = HR::cell(cs, t, k, off, &cr);
+        sP[k] = *at_node<CT>(Pn, m);
+        if (WALL) sGD[k] = (CT)(cs.grav[0] * off[0] + cs.grav[1] * off[1] + cs.grav[2] * off[2]);
     }
     __syncthreads();
-
-    // B: u = u* - D P / rho at every 1-halo cell.  A ghost cell takes the
-    // velocity of its mirror node with the sign flipped once per wall.
-    for (int k = threadIdx.x; k < R1::N; k += 256) {
-        const int ix = k % R1X, iy = (k / R1X) % R1Y, iz = k / (R1X * R1Y);
-        const int gx = t.ox - 1 + ix, gy = t.oy - 1 + iy, gz = t.oz - ZH + iz;
-        int sx = 0, sy = 0, sz = 0, cr = 0;
-        if (cs.wall[0]) { if (gx < 0) { sx = 1; ++cr; } else if (gx >= cs.nx) { sx = -1; ++cr; } }
-        if (cs.wall[1]) { if (gy < 0) { sy = 1; ++cr; } else if (gy >= cs.ny) { sy = -1; ++cr; } }
-        if (cs.wall[2]) { if (gz < 0) { sz = 1; ++cr; } else if (gz >= cs.nz) { sz = -1; ++cr; } }
-        const int mx = ix + sx + 1, my = iy + sy + 1, mz = iz + sz + ZH;  // mirror in R2 coordinates
-        const CT rho = ph.rho_a + clamp01(sPhi[k]) * ph.drho;
-        const CT irho = (CT)1 / rho;
-        CT gr[3] = {0, 0, 0};
-#pragma unroll
-        for (int i = 1; i < G::Q; i += 2) {
-            const int kp = R2::idx(mx + G::c(i, 0), my + G::c(i, 1), mz + G::c(i, 2));
-            const int km = R2::idx(mx - G::c(i, 0), my - G::c(i, 1), mz - G::c(i, 2));
-            const CT d = ((sP[kp] + rho * sGD[kp]) - (sP[km] + rho * sGD[km])) * (CT)G::w(i);
-#pragma unroll
-            for (int a = 0; a < DIMV; ++a) {
-                if (G::c(i, a) == 1) gr[a] += d;
-                if (G::c(i, a) == -1) gr[a] -= d;
-            }
-        }
-#pragma unroll
-        for (int a = 0; a < DIMV; ++a) {
-            CT ua = sU[a][k] - gr[a] * (CT)3.0 * irho;
-            sU[a][k] = (cr & 1) ? -ua : ua;
-        }
-    }
-    __syncthreads();
-
-    const int lx = threadIdx.x % Mo::TX, ly = (threadIdx.x / Mo::TX) % Mo::TY,
-              lz = threadIdx.x / (Mo::TX * Mo::TY);
+    int lx, ly, lz;
+    local_xyz<Mo>(&lx, &ly, &lz);
     const int x = t.ox + lx, y = t.oy + ly, z = t.oz + lz;
     if (x >= cs.nx || y >= cs.ny || z >= cs.nz) return;
-    const int64_t n = x + (int64_t)cs.nx * (y + (int64_t)cs.ny * z);
-    const int cx = lx + 1, cy = ly + 1, cz = lz + ZH;
-    const int c0 = R1::idx(cx, cy, cz);
-    if (READ) {
-        CT* U = (CT*)cs.U;
+    const uint32_t n = (uint32_t)x + (uint32_t)cs.nx * ((uint32_t)y + (uint32_t)cs.ny * (uint32_t)z);
+    const CT ra = (CT)cs.rho_a, dr = (CT)(cs.rho_w - cs.rho_a);
+    const CT rho = ra + clamp01(*at_node<CT>(cs.phi, n)) * dr;
+    const CT irho = rcp(rho);
+    const int cx = lx + 1, cy = ly + 1, cz = lz + HR::ZH;
+    CT gr[3] = {0, 0, 0};
 #pragma unroll
-        for (int a = 0; a < DIMV; ++a) U[a * N + n] = sU[a][c0];
-        return;
+    for (int i = 1; i < G::Q; i += 2) {
+        const int kp = R::idx(cx + G::c(i, 0), cy + G::c(i, 1), cz + G::c(i, 2));
+        const int km = R::idx(cx - G::c(i, 0), cy - G::c(i, 1), cz - G::c(i, 2));
+        const CT d = (WALL ? (sP[kp] + rho * sGD[kp]) - (sP[km] + rho * sGD[km]) : sP[kp] - sP[km]) * (CT)G::w(i);
+#pragma unroll
+        for (int a = 0; a < DIMV; ++a) {
+            if (G::c(i, a) == 1) gr[a] += d;
+            if (G::c(i, a) == -1) gr[a] -= d;
+        }
     }
+    const Slots<CT> Js = slots<CT>(cs.J, cs.N), Us = slots<CT>(cs.U, cs.N);
+    const uint32_t na = n * (uint32_t)sizeof(CT);
+#pragma unroll
+    for (int a = 0; a < DIMV; ++a) *Us.at(a, na) = *Js.at(a, na) - gr[a] * (CT)3.0 * irho;
+}
 
-    // C: gradients, collisions, AA write
-    NodeVals<CT> v;
+template <int DIMV, class CT>
+__global__ __launch_bounds__(256) void k_velocity(CaseTab cases, const int* tstart, int ncases,
+                                                  int total_tiles, int step_off)
+{
+    using Mo = Model<DIMV>;
+    using R = typename Halo1<Mo, DIMV>::R;
+    __shared__ CT sP[R::N], sGD[R::N];
+    const TileCtx t = tile_ctx<Mo>(cases, tstart, ncases, total_tiles, step_off);
+    if (!t.active) return;
+    CDesc& cs = *t.cs;
+    if (tile_at_wall<Mo>(cs, t.ox, t.oy, t.oz)) velocity_tile<DIMV, CT, true, R>(cs, t, sP, sGD);
+    else velocity_tile<DIMV, CT, false, R>(cs, t, sP, sGD);
+}
+
+// Gradients of phi, rho and u at interior cell (cx, cy, cz) of a 1-halo tile.
+template <int DIMV, class R, class CT>
+__device__ __forceinline__ void tile_gradients(const CT* sPhi, const CT* sRho, const CT (*sU)[R::N], int cx,
+                                               int cy, int cz, NodeVals<CT>& v)
+{
+    using G = typename Model<DIMV>::G;
+    const int c0 = R::idx(cx, cy, cz);
     v.phi = sPhi[c0];
 #pragma unroll
     for (int a = 0; a < 3; ++a) v.u[a] = a < DIMV ? sU[a][c0] : (CT)0;
-    stencil<G, R1, CT>([&](int k) { return sPhi[k]; }, cx, cy, cz, v.gphi, &v.lphi);
-    stencil<G, R1, CT>([&](int k) { return ph.rho_a + clamp01(sPhi[k]) * ph.drho; }, cx, cy, cz,
-                       v.grho, (CT*)nullptr);
+    stencil<G, R, CT>([&](int k) { return sPhi[k]; }, cx, cy, cz, v.gphi, &v.lphi);
+    PULBM_PHASE_FENCE();
+    stencil<G, R, CT>([&](int k) { return sRho[k]; }, cx, cy, cz, v.grho, (CT*)nullptr);
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int b = 0; b < 3; ++b) v.G[a][b] = 0;
 #pragma unroll
     for (int a = 0; a < DIMV; ++a) {
+        PULBM_PHASE_FENCE();
         CT gr[3];
-        stencil<G, R1, CT>([&](int k) { return sU[a][k]; }, cx, cy, cz, gr, (CT*)nullptr);
+        stencil<G, R, CT>([&](int k) { return sU[a][k]; }, cx, cy, cz, gr, (CT*)nullptr);
 #pragma unroll
         for (int b = 0; b < DIMV; ++b) v.G[a][b] = gr[b];
     }
+    PULBM_PHASE_FENCE();
+}
 
-    const bool odd = t.step & 1;
-    const Nav nv = make_nav(cs, x, y, z);
-    S* __restrict__ hp = (S*)cs.h;
-    S* __restrict__ gp = (S*)cs.g;
-    const CT hisc = (CT)cs.h_inv_scale, hsc = (CT)cs.h_scale;
-    const CT gsc = (CT)cs.g_scale;
-    const CT phr = (CT)cs.phi_ref;
-    CT hv[H::Q];
-#pragma unroll
-    for (int j = 0; j < H::Q; ++j)
-        hv[j] = Codec<S>::load(hp, aa_src<H>(nv, N, n, j, odd), hisc, phr * (CT)H::w(j));
+// --- collide + stream.  A tile first issues the loads of its own nodes'
+// incoming h (parked in LDS until the direction loop) and M2, together with
+// the halo loads of phi and u, so that their latencies overlap; then it takes
+// the gradients from LDS and collides one direction at a time.
+template <int DIMV, class S, bool WALL, class R>
+__device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typename Codec<S>::CT* sPhi,
+                                             typename Codec<S>::CT* sRho,
+                                             typename Codec<S>::CT (*sU)[R::N], S (*sH)[256])
+{
+    using Mo = Model<DIMV>;
+    using G = typename Mo::G;
+    using H = typename Mo::H;
+    using CT = typename Codec<S>::CT;
+    using HR = Halo1<Mo, DIMV>;
     constexpr int NM = DIMV == 2 ? 3 : 6;
+    const Phys<CT> ph = make_phys<CT>(cs);
+    int lx, ly, lz;
+    local_xyz<Mo>(&lx, &ly, &lz);
+    const int x = t.ox + lx, y = t.oy + ly, z = t.oz + lz;
+    const bool inside = x < cs.nx && y < cs.ny && z < cs.nz;
+    const uint32_t n = inside ? (uint32_t)x + (uint32_t)cs.nx * ((uint32_t)y + (uint32_t)cs.ny * (uint32_t)z) : 0u;
+    const uint32_t nb = n * (uint32_t)sizeof(S), na = n * (uint32_t)sizeof(CT);
+    const bool odd = t.step & 1;
+    const Nav nv = make_nav(cs, inside ? x : 0, inside ? y : 0, inside ? z : 0, (int)sizeof(S));
+    const Slots<S> hs = slots<S>(cs.h, cs.N), gs = slots<S>(cs.g, cs.N);
+    // own-node loads first
+    S hraw[H::Q];
     CT m2[NM];
-    const CT* __restrict__ M2v = (const CT*)cs.M2;
+    if (inside) {
 #pragma unroll
-    for (int k = 0; k < NM; ++k) m2[k] = M2v[k * N + n];
-    CT gv[G::Q];
-    CT F[3], rho;
-    node_physics<DIMV, false, CT>(ph, v, hv, m2, gv, F, &rho);
+        for (int j = 0; j < H::Q; ++j) hraw[j] = aa_load<H, WALL>(hs, nb, nv, j, odd);
+        const Slots<CT> Ms = slots<CT>(cs.M2, cs.N);
 #pragma unroll
-    for (int j = 0; j < H::Q; ++j) {
-        bool bb;
-        const int64_t d = aa_dst<H>(nv, N, n, j, odd, &bb);
-        Codec<S>::store(hp, d, hv[j], hsc, phr * (CT)H::w(j));
+        for (int k = 0; k < NM; ++k) m2[k] = *Ms.at(k, na);
     }
-    const CT corr = (CT)2 * (CT)3.0 / rho;  // 2 / (rho T)
+    // halo of phi, rho and u
+    const Slots<CT> Us = slots<CT>(cs.U, cs.N);
+    // fixed trip count, fully unrolled: every halo load is issued before the
+    // first LDS write waits on one
 #pragma unroll
-    for (int i = 0; i < G::Q; ++i) {
-        bool bb;
-        const int64_t d = aa_dst<G>(nv, N, n, i, odd, &bb);
-        CT val = gv[i];
-        if (bb) {
+    for (int it = 0; it < (R::N + 255) / 256; ++it) {
+        const int k = threadIdx.x + 256 * it;
+        if (k >= R::N) break;
+        int off[3], cr;
+        const uint32_t m = HR::cell(cs, t, k, off, &cr);
+        const CT f = *at_node<CT>(cs.phi, m);
+        sPhi[k] = f;
+        sRho[k] = ph.rho_a + clamp01(f) * ph.drho;
+#pragma unroll
+        for (int a = 0; a < DIMV; ++a) {
+            const CT ua = *Us.at(a, m * (uint32_t)sizeof(CT));
+            sU[a][k] = (WALL && (cr & 1)) ? -ua : ua;  // no slip on the half-link wall
+        }
+    }
+    if (inside) {
+#pragma unroll
+        for (int j = 0; j < H::Q; ++j) sH[j][threadIdx.x] = hraw[j];
+    }
+    __syncthreads();
+    if (!inside) return;
+
+    NodeVals<CT> v;
+    tile_gradients<DIMV, R, CT>(sPhi, sRho, sU, lx + 1, ly + 1, lz + HR::ZH, v);
+    const NodeCoef<DIMV, CT> kc = node_coef<DIMV, false, CT>(ph, v, m2);
+    const CT hisc = (CT)cs.h_inv_scale, hsc = (CT)cs.h_scale, gsc = (CT)cs.g_scale;
+    const CT phr = (CT)cs.phi_ref;
+    const CT corr = (CT)6.0 * rcp(kc.rho);  // 2 / (rho T)
+    // rest direction, then opposite pairs; both lattices share the direction
+    // order, so h_i and g_i stream to the same node
+    {
+        const CT g0 = g_out<G, DIMV, false>(v, kc, 0);
+        aa_store<G, WALL>(gs, nb, nv, 0, odd, Codec<S>::enc(g0, gsc, (CT)0), false);
+        const CT h0 = Codec<S>::dec(sH[0][threadIdx.x], hisc, phr * (CT)H::w(0));
+        aa_store<H, WALL>(hs, nb, nv, 0, odd,
+                          Codec<S>::enc(h_out<H, DIMV, false>(ph, v, kc, 0, h0), hsc, phr * (CT)H::w(0)), false);
+    }
+#pragma unroll
+    for (int i = 1; i < G::Q; i += 2) {
+        const bool bi = WALL && nav_solid<G>(nv, i, +1);
+        const bool bk = WALL && nav_solid<G>(nv, i + 1, +1);
+        CT gi, gk;
+        g_pair<G, DIMV, false>(v, kc, i, &gi, &gk);
+        if (WALL) {
             CT cF = 0;
 #pragma unroll
             for (int a = 0; a < DIMV; ++a) {
-                if (G::c(i, a) == 1) cF += F[a];
-                if (G::c(i, a) == -1) cF -= F[a];
+                if (G::c(i, a) == 1) cF += kc.F[a];
+                if (G::c(i, a) == -1) cF -= kc.F[a];
             }
-            val -= (CT)G::w(i) * cF * corr;
+            // a reflected population keeps the force part of its equilibrium
+            const CT fc = (CT)G::w(i) * cF * corr;
+            gi -= bi ? fc : (CT)0;
+            gk += bk ? fc : (CT)0;
         }
-        Codec<S>::store(gp, d, val, gsc, (CT)0);
+        aa_store<G, WALL>(gs, nb, nv, i, odd, Codec<S>::enc(gi, gsc, (CT)0), bi);
+        aa_store<G, WALL>(gs, nb, nv, i + 1, odd, Codec<S>::enc(gk, gsc, (CT)0), bk);
+        if (i < H::Q) {
+            const CT hi = Codec<S>::dec(sH[i][threadIdx.x], hisc, phr * (CT)H::w(i));
+            const CT hk = Codec<S>::dec(sH[i + 1][threadIdx.x], hisc, phr * (CT)H::w(i + 1));
+            CT oi, ok;
+            h_pair<H, DIMV, false>(ph, v, kc, i, hi, hk, &oi, &ok);
+            aa_store<H, WALL>(hs, nb, nv, i, odd, Codec<S>::enc(oi, hsc, phr * (CT)H::w(i)), bi);
+            aa_store<H, WALL>(hs, nb, nv, i + 1, odd, Codec<S>::enc(ok, hsc, phr * (CT)H::w(i + 1)), bk);
+        }
     }
+}
+
+template <int DIMV, class S>
+__global__ __launch_bounds__(256) void k_collide(CaseTab cases, const int* tstart, int ncases, int total_tiles,
+                                                 int step_off)
+{
+    using Mo = Model<DIMV>;
+    using H = typename Mo::H;
+    using CT = typename Codec<S>::CT;
+    using R = typename Halo1<Mo, DIMV>::R;
+    __shared__ CT sPhi[R::N], sRho[R::N], sU[DIMV][R::N];
+    __shared__ S sH[H::Q][256];
+    const TileCtx t = tile_ctx<Mo>(cases, tstart, ncases, total_tiles, step_off);
+    if (!t.active) return;
+    CDesc& cs = *t.cs;
+    if (tile_at_wall<Mo>(cs, t.ox, t.oy, t.oz)) collide_tile<DIMV, S, true, R>(cs, t, sPhi, sRho, sU, sH);
+    else collide_tile<DIMV, S, false, R>(cs, t, sPhi, sRho, sU, sH);
 }
 
 // --- initial state: equilibria of (phi0, P0, u0) in the even AA layout,
 //     previous-step pressure P[0] = P0.  Inputs are FP64 device arrays.
 template <int DIMV, class S>
-__global__ __launch_bounds__(256) void k_init(CaseTab cases, const int* __restrict__ tstart, int ncases,
-                                              int total_tiles, const double* __restrict__ phi0,
-                                              const double* __restrict__ P0,
+__global__ __launch_bounds__(256) void k_init(CaseTab cases, const int* tstart, int ncases, int total_tiles,
+                                              const double* __restrict__ phi0, const double* __restrict__ P0,
                                               const double* __restrict__ u0)
 {
     using Mo = Model<DIMV>;
     using G = typename Mo::G;
     using H = typename Mo::H;
     using CT = typename Codec<S>::CT;
-    constexpr int ZH = DIMV == 3 ? 1 : 0;
-    constexpr int R1X = Mo::TX + 2, R1Y = Mo::TY + 2, R1Z = Mo::TZ + 2 * ZH;
-    using R1 = Region<R1X, R1Y, R1Z>;
-    __shared__ CT sPhi[R1::N], sU[DIMV][R1::N];
+    using HR = Halo1<Mo, DIMV>;
+    using R = typename HR::R;
+    __shared__ CT sPhi[R::N], sRho[R::N], sU[DIMV][R::N];
     const TileCtx t = tile_ctx<Mo>(cases, tstart, ncases, total_tiles, 0);
     if (!t.active) return;
-    const CaseDev& cs = *cases[t.ci];
-    const int64_t N = cs.N;
+    CDesc& cs = *t.cs;
+    const uint32_t N = (uint32_t)cs.N;
     const Phys<CT> ph = make_phys<CT>(cs);
-    for (int k = threadIdx.x; k < R1::N; k += 256) {
-        const int ix = k % R1X, iy = (k / R1X) % R1Y, iz = k / (R1X * R1Y);
-        int off[3], cr = 0;
-        const int mx = resolve_axis(t.ox - 1 + ix, cs.nx, cs.wall[0], &off[0], &cr);
-        const int my = resolve_axis(t.oy - 1 + iy, cs.ny, cs.wall[1], &off[1], &cr);
-        const int mz = resolve_axis(t.oz - ZH + iz, cs.nz, cs.wall[2], &off[2], &cr);
-        const int64_t m = mx + (int64_t)cs.nx * (my + (int64_t)cs.ny * mz);
-        sPhi[k] = (CT)phi0[m];
+    // fixed trip count, fully unrolled: every halo load is issued before the
+    // first LDS write waits on one
+#pragma unroll
+    for (int it = 0; it < (R::N + 255) / 256; ++it) {
+        const int k = threadIdx.x + 256 * it;
+        if (k >= R::N) break;
+        int off[3], cr;
+        const uint32_t m = HR::cell(cs, t, k, off, &cr);
+        const CT f = (CT)phi0[m];
+        sPhi[k] = f;
+        sRho[k] = ph.rho_a + clamp01(f) * ph.drho;
 #pragma unroll
         for (int a = 0; a < DIMV; ++a) {
-            const CT ua = (CT)u0[a * N + m];
+            const CT ua = (CT)u0[(size_t)a * N + m];
             sU[a][k] = (cr & 1) ? -ua : ua;
         }
     }
     __syncthreads();
-    const int lx = threadIdx.x % Mo::TX, ly = (threadIdx.x / Mo::TX) % Mo::TY,
-              lz = threadIdx.x / (Mo::TX * Mo::TY);
+    int lx, ly, lz;
+    local_xyz<Mo>(&lx, &ly, &lz);
     const int x = t.ox + lx, y = t.oy + ly, z = t.oz + lz;
     if (x >= cs.nx || y >= cs.ny || z >= cs.nz) return;
-    const int64_t n = x + (int64_t)cs.nx * (y + (int64_t)cs.ny * z);
-    const int cx = lx + 1, cy = ly + 1, cz = lz + ZH;
-    const int c0 = R1::idx(cx, cy, cz);
+    const uint32_t n = (uint32_t)x + (uint32_t)cs.nx * ((uint32_t)y + (uint32_t)cs.ny * (uint32_t)z);
     NodeVals<CT> v;
-    v.phi = sPhi[c0];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) v.u[a] = a < DIMV ? sU[a][c0] : (CT)0;
-    stencil<G, R1, CT>([&](int k) { return sPhi[k]; }, cx, cy, cz, v.gphi, &v.lphi);
-    stencil<G, R1, CT>([&](int k) { return ph.rho_a + clamp01(sPhi[k]) * ph.drho; }, cx, cy, cz,
-                       v.grho, (CT*)nullptr);
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) v.G[a][b] = 0;
-#pragma unroll
-    for (int a = 0; a < DIMV; ++a) {
-        CT gr[3];
-        stencil<G, R1, CT>([&](int k) { return sU[a][k]; }, cx, cy, cz, gr, (CT*)nullptr);
-#pragma unroll
-        for (int b = 0; b < DIMV; ++b) v.G[a][b] = gr[b];
-    }
-    CT hv[H::Q], gv[G::Q], F[3], rho;
-    node_physics<DIMV, true, CT>(ph, v, hv, (const CT*)nullptr, gv, F, &rho);
-    S* __restrict__ hp = (S*)cs.h;
-    S* __restrict__ gp = (S*)cs.g;
+    tile_gradients<DIMV, R, CT>(sPhi, sRho, sU, lx + 1, ly + 1, lz + HR::ZH, v);
+    const NodeCoef<DIMV, CT> kc = node_coef<DIMV, true, CT>(ph, v, (const CT*)nullptr);
+    const Slots<S> hs = slots<S>(cs.h, cs.N), gs = slots<S>(cs.g, cs.N);
+    const uint32_t nb = n * (uint32_t)sizeof(S);
     const CT hsc = (CT)cs.h_scale, gsc = (CT)cs.g_scale, phr = (CT)cs.phi_ref;
 #pragma unroll
-    for (int j = 0; j < H::Q; ++j) Codec<S>::store(hp, (int64_t)j * N + n, hv[j], hsc, phr * (CT)H::w(j));
+    for (int j = 0; j < H::Q; ++j)
+        *hs.at(j, nb) = Codec<S>::enc(h_out<H, DIMV, true>(ph, v, kc, j, (CT)0), hsc, phr * (CT)H::w(j));
 #pragma unroll
-    for (int i = 0; i < G::Q; ++i) Codec<S>::store(gp, (int64_t)i * N + n, gv[i], gsc, (CT)0);
-    ((CT*)cs.P[0])[n] = (CT)P0[n];
+    for (int i = 0; i < G::Q; ++i) *gs.at(i, nb) = Codec<S>::enc(g_out<G, DIMV, true>(v, kc, i), gsc, (CT)0);
+    *at_node<CT>(cs.P[0], n) = (CT)P0[n];
 }
 
 // --- step counters: every case of a table advances by k (up to its end).

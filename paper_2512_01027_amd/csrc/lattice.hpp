@@ -66,10 +66,15 @@ template <> struct Model<2> {
     using H = D2Q9;
     static constexpr int TX = 64, TY = 4, TZ = 1;
 };
-template <> struct Model<3> {
+#ifndef PULBM_TILE3
+#define PULBM_TILE3 32, 4, 2
+#endif
+template <int X, int Y, int Z> struct Tile3 {
+    static constexpr int TX = X, TY = Y, TZ = Z;
+};
+template <> struct Model<3> : Tile3<PULBM_TILE3> {
     using G = D3Q27;
     using H = D3Q19;
-    static constexpr int TX = 32, TY = 4, TZ = 2;
 };
 
 }  // namespace pulbm

@@ -120,6 +120,9 @@ template <int DIMV> void tiles_of(const pulbm_params& p, int* ntx, int* nty, int
 
 int grid_of(int tiles) { return ((tiles + 7) / 8) * 8; }
 
+constexpr int kStepKernels = 4;  // moments, pressure, velocity, collide + stream
+constexpr int kReadKernels = 3;  // the moment stage only
+
 }  // namespace
 
 struct pulbm_case {
@@ -149,8 +152,8 @@ void launch_step(hipStream_t st, CaseDev* const* tab, const int* tstart, int nca
     const dim3 grid(grid_of(tiles)), block(256);
     if (which == 0) hipLaunchKernelGGL((k_moments<DIMV, S>), grid, block, 0, st, tab, tstart, ncases, tiles, off);
     if (which == 1) hipLaunchKernelGGL((k_pressure<DIMV, CT>), grid, block, 0, st, tab, tstart, ncases, tiles, off);
-    if (which == 2) hipLaunchKernelGGL((k_collide<DIMV, S, false>), grid, block, 0, st, tab, tstart, ncases, tiles, off);
-    if (which == 3) hipLaunchKernelGGL((k_collide<DIMV, S, true>), grid, block, 0, st, tab, tstart, ncases, tiles, off);
+    if (which == 2) hipLaunchKernelGGL((k_velocity<DIMV, CT>), grid, block, 0, st, tab, tstart, ncases, tiles, off);
+    if (which == 3) hipLaunchKernelGGL((k_collide<DIMV, S>), grid, block, 0, st, tab, tstart, ncases, tiles, off);
 }
 
 template <int DIMV>
@@ -161,11 +164,11 @@ void launch_dim(int store, hipStream_t st, CaseDev* const* tab, const int* tstar
         case PULBM_STORE_FP64: launch_step<DIMV, double>(st, tab, tstart, ncases, tiles, off, which); break;
         case PULBM_STORE_FP32: launch_step<DIMV, float>(st, tab, tstart, ncases, tiles, off, which); break;
         case PULBM_STORE_FP16: launch_step<DIMV, _Float16>(st, tab, tstart, ncases, tiles, off, which); break;
-        default: launch_step<DIMV, bf16_t>(st, tab, tstart, ncases, tiles, off, which); break;
+        default: launch_step<DIMV, uint16_t>(st, tab, tstart, ncases, tiles, off, which); break;
     }
 }
 
-// which: 0 moments, 1 pressure, 2 collide, 3 read-pass velocity
+// which: 0 moments, 1 pressure, 2 velocity, 3 collide + stream
 void launch(int dim, int store, hipStream_t st, CaseDev* const* tab, const int* tstart, int ncases, int tiles,
             int off, int which)
 {
@@ -188,7 +191,7 @@ void launch_init(int dim, int store, hipStream_t st, CaseDev* const* tab, const 
         case PULBM_STORE_FP64: launch_init_t<D, double>(st, tab, tstart, tiles, phi, P, u); break;  \
         case PULBM_STORE_FP32: launch_init_t<D, float>(st, tab, tstart, tiles, phi, P, u); break;   \
         case PULBM_STORE_FP16: launch_init_t<D, _Float16>(st, tab, tstart, tiles, phi, P, u); break;\
-        default: launch_init_t<D, bf16_t>(st, tab, tstart, tiles, phi, P, u); break;                \
+        default: launch_init_t<D, uint16_t>(st, tab, tstart, tiles, phi, P, u); break;                \
     }
     if (dim == 2) { PULBM_INIT_CASE(2) } else { PULBM_INIT_CASE(3) }
 #undef PULBM_INIT_CASE
@@ -216,8 +219,7 @@ int upload_desc(pulbm_case* c)
 
 int read_pass(pulbm_case* c)
 {
-    for (int w = 0; w < 2; ++w) launch(c->p.dim, c->p.store, c->stream, c->tab, c->tstart, 1, c->ntiles, 0, w);
-    launch(c->p.dim, c->p.store, c->stream, c->tab, c->tstart, 1, c->ntiles, 0, 3);
+    for (int w = 0; w < kReadKernels; ++w) launch(c->p.dim, c->p.store, c->stream, c->tab, c->tstart, 1, c->ntiles, 0, w);
     HIPC(hipGetLastError());
     return PULBM_OK;
 }
@@ -375,7 +377,8 @@ static int queue_steps(pulbm_case* c, int64_t nsteps)
     for (int64_t s = 0; s < nsteps;) {
         const int chunk = (int)std::min<int64_t>(nsteps - s, 1 << 20);
         for (int k = 0; k < chunk; ++k)
-            for (int w = 0; w < 3; ++w) launch(c->p.dim, c->p.store, c->stream, c->tab, c->tstart, 1, c->ntiles, k, w);
+            for (int w = 0; w < kStepKernels; ++w)
+                launch(c->p.dim, c->p.store, c->stream, c->tab, c->tstart, 1, c->ntiles, k, w);
         hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, c->stream, c->tab, 1, chunk);
         HIPC(hipGetLastError());
         s += chunk;
@@ -397,23 +400,23 @@ extern "C" int pulbm_step_timed(pulbm_case* c, int64_t nsteps, double* ms)
 {
     if (!c || !ms) return fail(PULBM_EINVAL, "NULL argument");
     if (!c->ready) return fail(PULBM_ESTATE, "pulbm_step_timed before pulbm_init_fields");
-    hipEvent_t ev[4];
-    for (int k = 0; k < 4; ++k) HIPC(hipEventCreate(&ev[k]));
+    hipEvent_t ev[kStepKernels + 1];
+    for (int k = 0; k <= kStepKernels; ++k) HIPC(hipEventCreate(&ev[k]));
     int rc = PULBM_OK;
     for (int64_t s = 0; s < nsteps && rc == PULBM_OK; ++s) {
         (void)hipEventRecord(ev[0], c->stream);
-        for (int w = 0; w < 3; ++w) {
+        for (int w = 0; w < kStepKernels; ++w) {
             launch(c->p.dim, c->p.store, c->stream, c->tab, c->tstart, 1, c->ntiles, 0, w);
             (void)hipEventRecord(ev[w + 1], c->stream);
         }
         hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, c->stream, c->tab, 1, 1);
         hipError_t e = hipGetLastError();
-        if (e == hipSuccess) e = hipEventSynchronize(ev[3]);
+        if (e == hipSuccess) e = hipEventSynchronize(ev[kStepKernels]);
         if (e != hipSuccess) {
             rc = fail(PULBM_EDEVICE, "timed step failed: %s", hipGetErrorString(e));
             break;
         }
-        for (int w = 0; w < 3; ++w) {
+        for (int w = 0; w < kStepKernels; ++w) {
             float t = 0.f;
             (void)hipEventElapsedTime(&t, ev[w], ev[w + 1]);
             ms[w] += t;
@@ -421,7 +424,7 @@ extern "C" int pulbm_step_timed(pulbm_case* c, int64_t nsteps, double* ms)
         c->step += 1;
     }
     c->h.step = c->step;
-    for (int k = 0; k < 4; ++k) (void)hipEventDestroy(ev[k]);
+    for (int k = 0; k <= kStepKernels; ++k) (void)hipEventDestroy(ev[k]);
     if (rc == PULBM_OK) HIPC(hipStreamSynchronize(c->stream));
     return rc;
 }
@@ -702,7 +705,8 @@ extern "C" int pulbm_batch_advance(pulbm_batch* b, int32_t ksteps)
             hipGraphExec_t ge = nullptr;
             HIPC(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
             for (int k = 0; k < ksteps; ++k)
-                for (int w = 0; w < 3; ++w) launch(di + 2, b->store, b->stream, t.dtab, t.dts, t.ncases, t.tiles, k, w);
+                for (int w = 0; w < kStepKernels; ++w)
+                    launch(di + 2, b->store, b->stream, t.dtab, t.dts, t.ncases, t.tiles, k, w);
             hipLaunchKernelGGL(k_advance, dim3((t.ncases + 63) / 64), dim3(64), 0, b->stream, t.dtab, t.ncases, ksteps);
             HIPC(hipStreamEndCapture(b->stream, &g));
             HIPC(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
