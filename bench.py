@@ -1,14 +1,25 @@
 """Benchmark of the coupled phase-field + P-u LBE step on one MI355X.
 
-Workload (default): the 3D 128^3 periodic droplet (R = 24, rho ratio 1000,
-W = 4, sigma = 0.005, nu = 0.05) translated with u = (0.05, 0.02, 0),
-D3Q27 hydro + D3Q19 phase field, FP32 storage and compute.  A step is one
-full coupled time step (moments, pressure, collide + stream) of the whole
-grid; the state is resident in HBM before timing starts.
+Workload (the headline line): the 3D 128^3 periodic droplet (R = 24, density
+ratio 1000, W = 4, sigma = 0.005, nu = 0.05) translated with
+u = (0.05, 0.02, 0), D3Q27 hydro + D3Q19 phase field, FP32 storage and
+compute.  A step is one full coupled time step of the whole grid (moments,
+pressure, velocity, collide + stream); the state is resident in HBM before
+timing starts.  Synthetic, seeded inputs.
 
-Prints one JSON line: MLUPS of the whole step, the roofline of the dominant
-kernel (collide + stream) from HIP-event times, the same workload with FP16
-storage, and the CPU reference timed on a bounded sample on the host.
+Printed as one JSON line:
+  value          MLUPS of the whole step (wall clock over --steps steps)
+  roofline       the dominant kernel (collide + stream): algorithmic bytes per
+                 launch / its average HIP-event time, against 8 TB/s; traffic
+                 = HBM bytes per launch from the committed rocprofv3 counter
+                 summary when it was taken on the current kernel sources
+  hbm            state bytes per node-update x MLUPS, against the peak and
+                 against a device copy measured here
+  fp16_store     the same workload with FP16 storage
+  serving        a seeded Poisson stream of droplet / bubble requests served
+                 by continuous batching, p50 / p99 latency and aggregate MLUPS,
+                 beside the same stream run one case at a time
+  cpu_baseline   the FP64 CPU reference on a bounded sample of the workload
 """
 from __future__ import annotations
 
@@ -18,27 +29,29 @@ import os
 import sys
 import time
 
-import numpy as np
-
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+METRIC = "coupled-lattice MLUPS, % HBM peak; p50/p99 case latency; FP16 vs FP32 store"
+COUNTERS = os.path.join(ROOT, "profiles", "galilean_droplet_128cube_hbm_counters.txt")
 # Algorithmic bytes per node of each kernel, 3D D3Q27 + D3Q19 (values per node
 # times their width, each read or written once): moments reads 46 populations
 # and writes phi, u*(3), S, M2(6); pressure reads u*(3), P, phi, S and writes
 # P; velocity reads P, u*(3), phi and writes u(3); collide reads phi, u(3),
-# M2(6), h(19) and writes 46 populations.
+# M2(6), h(19) and writes 46 populations.  2-byte storage also reads the
+# previous-step phi in moments and collide (the h codec's reference).
 POP_VALUES_3D = 46
 KERNELS = ("moments", "pressure", "velocity", "collide")
 
 
 def kernel_bytes(store_bytes, aux_bytes=4):
+    ref = aux_bytes if store_bytes == 2 else 0
     return {
-        "moments": POP_VALUES_3D * store_bytes + 11 * aux_bytes,
+        "moments": POP_VALUES_3D * store_bytes + ref + 11 * aux_bytes,
         "pressure": 7 * aux_bytes,
         "velocity": 8 * aux_bytes,
-        "collide": 19 * store_bytes + 10 * aux_bytes + POP_VALUES_3D * store_bytes,
+        "collide": 19 * store_bytes + ref + 10 * aux_bytes + POP_VALUES_3D * store_bytes,
     }
 
 
@@ -62,11 +75,65 @@ def run_gpu(cfg, fields, steps, warmup):
     c.sync()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    ms = c.step_timed(max(3, min(steps, 20)))
     nt = max(3, min(steps, 20))
+    ms = c.step_timed(nt)
     d = c.diagnostics(allow_diverged=True)
     c.close()
     return dt, ms / nt, d
+
+
+def copy_bandwidth(mib=1024, reps=5):
+    """Read + write GB/s of a plain device copy (torch)."""
+    import torch
+
+    src = torch.ones(mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    gbs = 2 * src.numel() * 4 / dt / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return round(gbs, 1)
+
+
+def traffic_of(kernel_name, n):
+    """HBM bytes per launch of a kernel from the committed counter summary,
+    if it was taken on the current kernel sources for this grid."""
+    from paper_2512_01027_amd import profsum
+
+    rec = profsum.load_traffic(COUNTERS)
+    if rec is None or rec["source_sha256"] != profsum.source_hash() or rec["nodes"] != n ** 3:
+        return None
+    k = rec["kernels"].get(kernel_name)
+    return None if k is None else int(round(k["read_bytes"] + k["write_bytes"]))
+
+
+def serving_leg(fp16_mlups, n_cases=64, step_scale=0.1):
+    import torch
+
+    from paper_2512_01027_amd import serving as SV
+
+    reqs = SV.make_stream(n_cases, "fp16", step_scale)
+    mean_work = sum(r.work for r in reqs) / len(reqs)
+    rate = 0.8 * fp16_mlups * 1e6 / mean_work
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(0.8 * free)
+    SV.set_arrivals(reqs, rate)
+    b = SV.run_batched(reqs, budget)
+    SV.set_arrivals(reqs, rate)
+    s = SV.run_sequential(reqs)
+    rep = SV.ServingReport(b, s).as_dict()
+    rep["sample"] = (f"{n_cases} requests (seed 3): 75% 3D n in [32,192], 25% 2D n in [128,1024] "
+                     f"(log-uniform), droplet / rising bubble, density ratio 10/100/1000, "
+                     f"steps U{{1000..10000}} x {step_scale}; Poisson arrivals (seed 2) at "
+                     f"{rate:.2f}/s = 0.8 x FP16 capacity / mean work; FP16 storage; "
+                     f"budget {budget / 2**30:.0f} GiB")
+    return rep
 
 
 def cpu_baseline(cfg, fields):
@@ -94,27 +161,16 @@ def main():
     ap.add_argument("--n", type=int, default=128, help="grid edge of the 3D droplet workload")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp16", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
     if args.copy_probe:
-        import torch
-
-        src = torch.ones(args.copy_probe * (1 << 20) // 4, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(5):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / 5
-        nbytes = src.numel() * 4
-        print(json.dumps({"copy_probe_bytes": nbytes, "dispatches": 6,
-                          "copy_GBs_read_plus_write": round(2 * nbytes / dt / 1e9, 1)}))
+        print(json.dumps({"copy_probe_bytes": args.copy_probe << 20, "dispatches": 6,
+                          "copy_GBs_read_plus_write": copy_bandwidth(args.copy_probe)}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
 
     from paper_2512_01027_amd import workloads as W
@@ -125,8 +181,10 @@ def main():
     mlups = N * args.steps / dt / 1e6
     kb = kernel_bytes(4)
     ach = kb["collide"] * N / (ms[3] * 1e-3) / 1e9
+    copy_gbs = copy_bandwidth()
+    eff = mlups * 1e6 * state_bytes(4) / 1e9
     out = {
-        "metric": "coupled-lattice MLUPS (D3Q27 hydro + D3Q19 phase field)",
+        "metric": METRIC,
         "value": round(mlups, 2),
         "unit": "MLUPS",
         "n_gpus": 1,
@@ -138,22 +196,31 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"3D {args.n}^3 periodic translated droplet R={24 * args.n // 128}, "
-                               "rho ratio 1000, FP32 store", "nodes": N, "store": "fp32"},
-        "roofline": {"bound": "hbm", "kernel": "k_collide", "achieved": round(ach, 1),
+        "config": {"workload": f"3D {args.n}^3 periodic droplet R={24 * args.n // 128} translated with "
+                               "u=(0.05,0.02,0), rho ratio 1000, D3Q27 hydro + D3Q19 phase field, "
+                               "FP32 store and compute", "nodes": N, "store": "fp32"},
+        "roofline": {"bound": "hbm", "kernel": "k_collide<3, float>", "achieved": round(ach, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                     "traffic": None},
+                     "traffic": traffic_of("pulbm::k_collide<3, float>", args.n),
+                     "algorithmic_bytes_per_launch": kb["collide"] * N},
+        "hbm": {"state_bytes_per_node_update": state_bytes(4), "effective_GBs": round(eff, 1),
+                "frac_of_peak": round(eff / HBM_PEAK_GBS, 4), "device_copy_GBs": copy_gbs,
+                "frac_of_copy": round(eff / copy_gbs, 4)},
         "kernel_ms": {k: round(float(v), 4) for k, v in zip(KERNELS, ms)},
         "kernel_GBs": {k: round(kb[k] * N / (float(v) * 1e-3) / 1e9, 1) for k, v in zip(KERNELS, ms)},
-        "effective_state_GBs": round(mlups * 1e6 * state_bytes(4) / 1e9, 1),
         "nonfinite": diag["nonfinite"],
     }
     if not args.no_fp16:
         cfg16 = dict(cfg, store="fp16")
         dt16, ms16, _ = run_gpu(cfg16, fields, args.steps, args.warmup)
-        out["fp16_store"] = {"value": round(N * args.steps / dt16 / 1e6, 2), "unit": "MLUPS",
-                             "ratio_vs_fp32": round(dt / dt16, 3),
-                             "kernel_ms": {k: round(float(v), 4) for k, v in zip(KERNELS, ms16)}}
+        kb16 = kernel_bytes(2)
+        m16 = N * args.steps / dt16 / 1e6
+        out["fp16_store"] = {"value": round(m16, 2), "unit": "MLUPS", "ratio_vs_fp32": round(dt / dt16, 3),
+                             "kernel_ms": {k: round(float(v), 4) for k, v in zip(KERNELS, ms16)},
+                             "collide_GBs": round(kb16["collide"] * N / (ms16[3] * 1e-3) / 1e9, 1),
+                             "effective_GBs": round(m16 * 1e6 * state_bytes(2) / 1e9, 1)}
+        if not args.no_serving:
+            out["serving"] = serving_leg(m16)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, fields)
     print(json.dumps(out))

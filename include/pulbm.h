@@ -46,12 +46,16 @@ extern "C" {
 /* Storage precision of the distributions (compute precision in brackets). */
 #define PULBM_STORE_FP64 0 /* FP64 (FP64)                                             */
 #define PULBM_STORE_FP32 1 /* FP32 (FP32; pressure reconstruction and sums in FP64)   */
-#define PULBM_STORE_FP16 2 /* FP16 shifted and scaled populations (FP32 compute)      */
-#define PULBM_STORE_BF16 3 /* BF16 shifted populations (FP32 compute)                 */
+#define PULBM_STORE_FP16 2 /* FP16 shifted and scaled populations (FP32 compute):   */
+                           /* h_j - w_j phi (phi of the reading node, previous     */
+                           /* step) and g_i (already small: its pressure part is   */
+                           /* kept apart), scaled by powers of two                 */
+#define PULBM_STORE_BF16 3 /* BF16, the same shifted populations (FP32 compute)     */
 
 /* Case parameters, lattice units (Sec. II; defaults of Sec. III in brackets). */
 typedef struct {
-    int32_t dim, nx, ny, nz;     /* dim 2 (nz = 1) or 3; every n >= 1                      */
+    int32_t dim, nx, ny, nz;     /* dim 2 (nz = 1) or 3; every n >= 1; nx*ny*nz below 2^28
+                                    nodes in FP64 storage, below 2^29 otherwise             */
     int32_t q_hydro, q_phase;    /* 2D: 9, 9; 3D: 27, 19 (hydro D3Q27, phase field D3Q19)   */
     int32_t wall[3];             /* per axis: 0 periodic, 1 no-slip walls at both ends      */
     int32_t delta_theta;         /* 1: apply the delta-theta correction of Sec. II [1]      */
@@ -62,8 +66,6 @@ typedef struct {
     double sigma, W, M;          /* surface tension, interface width, mobility [M = 0.166]  */
     double lambda_bulk;          /* bulk viscosity [1/6]                                    */
     double gravity[3];           /* body force per unit mass, F_ext = rho g                 */
-    double phi_ref;              /* FP16/BF16: h is stored as h_j - w_j phi_ref; a negative
-                                    value lets init_fields pick 0 or 1 from the mean of phi0 */
 } pulbm_params;
 
 typedef struct {
@@ -107,7 +109,8 @@ int pulbm_read_fields(pulbm_case* c, double* phi, double* P, double* u);
 int pulbm_diagnostics(pulbm_case* c, pulbm_diag* d);
 
 /* Restart image (distributions in their storage precision, previous-step
- * pressure, step count, parameters).  checkpoint_bytes gives the size. */
+ * pressure and phi, step count, parameters).  checkpoint_bytes gives the
+ * size. */
 int pulbm_checkpoint_bytes(const pulbm_case* c, size_t* bytes);
 int pulbm_checkpoint(pulbm_case* c, void* host_buf, size_t bytes);
 int pulbm_restore(pulbm_case* c, const void* host_buf, size_t bytes);

@@ -43,7 +43,7 @@ class Params(C.Structure):
         ("rho_heavy", C.c_double), ("rho_light", C.c_double),
         ("nu_heavy", C.c_double), ("nu_light", C.c_double),
         ("sigma", C.c_double), ("W", C.c_double), ("M", C.c_double),
-        ("lambda_bulk", C.c_double), ("gravity", C.c_double * 3), ("phi_ref", C.c_double),
+        ("lambda_bulk", C.c_double), ("gravity", C.c_double * 3),
     ]
 
 
@@ -143,7 +143,6 @@ def make_params(cfg: dict) -> Params:
     gv = list(cfg.get("gravity", (0.0, 0.0, 0.0))) + [0.0, 0.0, 0.0]
     for a in range(3):
         p.gravity[a] = float(gv[a])
-    p.phi_ref = float(cfg.get("phi_ref", -1.0))
     return p
 
 

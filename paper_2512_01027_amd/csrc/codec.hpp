@@ -2,9 +2,10 @@
 //
 // FP64 and FP32 store values as they are.  FP16 and BF16 store shifted and
 // scaled populations, (f - shift) * scale, rounded to nearest-even; loads
-// invert that in FP32.  Shift removes the part every node shares (w_j * phi_ref
-// for h); scale (a power of two) lifts small populations out of the FP16
-// subnormal range.  BF16 rounding is written out from the IEEE-754 binary32
+// invert that in FP32.  The shift removes the large part of a population that
+// its reader can rebuild on its own (w_j times its own phi of the step before,
+// for h); the scale (a power of two) lifts the small remainder out of the
+// FP16 subnormal range.  BF16 rounding is written out from the IEEE-754 binary32
 // layout: keep the upper 16 bits, round half to even, keep NaNs quiet.
 #pragma once
 #include <hip/hip_runtime.h>

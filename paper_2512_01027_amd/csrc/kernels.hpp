@@ -54,14 +54,15 @@ struct CaseDev {
     void* h;           // Q_h * N populations (storage type)
     void* g;           // Q_g * N populations (storage type)
     void* P[2];        // pressure ping-pong: P[step & 1] is the previous-step pressure
-    void* phi;         // N      scratch (aux type)
+    void* phi[2];      // N each: phi of this step's moments at phi[step & 1]; phi[(step + 1) & 1]
+                       // keeps the previous step's, the reference of the 2-byte h codec
     void* J;           // dim*N  scratch: u* = sum g c
     void* S;           // N      scratch: rho_ref T (sum g without the pressure part)
     void* M2;          // 3 (2D) or 6 (3D) * N scratch: sum g c c
     void* U;           // dim*N  velocity u of the current step
     double rho_a, rho_w, tau_a, tau_w, tau_phi, M, W, sigma, lambda_b;
     double grav[3];
-    double h_scale, h_inv_scale, g_scale, g_inv_scale, phi_ref;
+    double h_scale, h_inv_scale, g_scale, g_inv_scale;
 };
 
 using CDesc = const PULBM_CST CaseDev;
@@ -215,43 +216,49 @@ __device__ __forceinline__ bool tile_at_wall(CDesc& cs, int ox, int oy, int oz)
 }
 
 // Population loads and stores.  The populations of a step are read once and
-// written once and the state is far larger than the caches, so they can be
-// marked non-temporal.
-template <class S> __device__ __forceinline__ S pop_ld(const PULBM_GLB S* p)
-{
-#ifdef PULBM_NT_LOAD
-    return __builtin_nontemporal_load(p);
-#else
-    return *p;
+// written once, and at the sizes that matter the state is far larger than the
+// caches, so accesses can be marked non-temporal.  Which accesses gain from it
+// was measured per storage width (bit 0: loads in k_moments, bit 1: loads in
+// k_collide, bit 2: stores in k_collide): 4- and 8-byte populations stream
+// their loads, 2-byte populations their stores.
+#ifndef PULBM_NT_WIDE
+#define PULBM_NT_WIDE 3
 #endif
+#ifndef PULBM_NT_HALF
+#define PULBM_NT_HALF 4
+#endif
+enum PopAccess { kLoadMoments = 1, kLoadCollide = 2, kStoreCollide = 4 };
+template <class S, int A> constexpr bool nt_access() { return ((sizeof(S) >= 4 ? PULBM_NT_WIDE : PULBM_NT_HALF) & A) != 0; }
+
+template <bool NT, class S> __device__ __forceinline__ S pop_ld(const PULBM_GLB S* p)
+{
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
 }
-template <class S> __device__ __forceinline__ void pop_st(PULBM_GLB S* p, S v)
+template <bool NT, class S> __device__ __forceinline__ void pop_st(PULBM_GLB S* p, S v)
 {
-#ifdef PULBM_NT_STORE
-    __builtin_nontemporal_store(v, p);
-#else
-    *p = v;
-#endif
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
 }
 
 // Population arriving at the node (byte offset nb) along direction i.
-template <class L, bool WALL, class S>
+template <class L, bool WALL, bool NT, class S>
 __device__ __forceinline__ S aa_load(const Slots<S>& f, uint32_t nb, const Nav& v, int i, bool odd)
 {
-    if (!odd) return pop_ld(f.at(i, nb));
-    if (WALL && nav_solid<L>(v, i, -1)) return pop_ld(f.at(i, nb));  // reflected at a wall last step
-    return pop_ld(f.at(opp(i), nb + (uint32_t)nav_off<L>(v, i, -1)));
+    if (!odd) return pop_ld<NT>(f.at(i, nb));
+    if (WALL && nav_solid<L>(v, i, -1)) return pop_ld<NT>(f.at(i, nb));  // reflected at a wall last step
+    return pop_ld<NT>(f.at(opp(i), nb + (uint32_t)nav_off<L>(v, i, -1)));
 }
 
 // Store the node's post-collision population i where it streams to; a
 // population leaving through a wall goes to the slot the node reads back as
 // the reflected direction.
-template <class L, bool WALL, class S>
+template <class L, bool WALL, bool NT, class S>
 __device__ __forceinline__ void aa_store(const Slots<S>& f, uint32_t nb, const Nav& v, int i, bool odd, S val,
                                          bool bb)
 {
-    if (!odd || (WALL && bb)) pop_st(f.at(opp(i), nb), val);
-    else pop_st(f.at(i, nb + (uint32_t)nav_off<L>(v, i, +1)), val);
+    if (!odd || (WALL && bb)) pop_st<NT>(f.at(opp(i), nb), val);
+    else pop_st<NT>(f.at(i, nb + (uint32_t)nav_off<L>(v, i, +1)), val);
 }
 
 // ---------------------------------------------------------- tile regions
@@ -588,6 +595,15 @@ __device__ __forceinline__ void local_xyz(int* lx, int* ly, int* lz)
 
 // ================================================================ kernels
 
+// phi of this node one step earlier: the reference of the incoming h in
+// 2-byte storage (wider storage keeps h as it is and reads nothing).
+template <class S, class CT = typename Codec<S>::CT>
+__device__ __forceinline__ CT h_reference(void* phi_prev, uint32_t n)
+{
+    if constexpr (sizeof(S) == 2) return *at_node<CT>(phi_prev, n);
+    else return (CT)0;
+}
+
 // --- moments: phi, u* = sum g c, S, M2 (per node; no halo)
 template <int DIMV, class S, bool WALL>
 __device__ __forceinline__ void moments_node(CDesc& cs, int x, int y, int z, bool odd)
@@ -601,14 +617,17 @@ __device__ __forceinline__ void moments_node(CDesc& cs, int x, int y, int z, boo
     const Nav nv = make_nav(cs, x, y, z, (int)sizeof(S));
     const Slots<S> hs = slots<S>(cs.h, cs.N), gs = slots<S>(cs.g, cs.N);
     const CT hsc = (CT)cs.h_inv_scale, gsc = (CT)cs.g_inv_scale;
-    const CT phr = (CT)cs.phi_ref;
+    // 2-byte storage holds h_j - w_j phi, phi of this node one step earlier
+    const CT php = h_reference<S>(cs.phi[odd ? 0 : 1], n);
     CT phi = 0;
 #pragma unroll
-    for (int j = 0; j < H::Q; ++j) phi += Codec<S>::dec(aa_load<H, WALL>(hs, nb, nv, j, odd), hsc, phr * (CT)H::w(j));
+    for (int j = 0; j < H::Q; ++j)
+        phi += Codec<S>::dec(aa_load<H, WALL, nt_access<S, kLoadMoments>()>(hs, nb, nv, j, odd), hsc,
+                             php * (CT)H::w(j));
     CT sum = 0, J[3] = {0, 0, 0}, m2[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
     for (int i = 0; i < G::Q; ++i) {
-        const CT f = Codec<S>::dec(aa_load<G, WALL>(gs, nb, nv, i, odd), gsc, (CT)0);
+        const CT f = Codec<S>::dec(aa_load<G, WALL, nt_access<S, kLoadMoments>()>(gs, nb, nv, i, odd), gsc, (CT)0);
         sum += f;
 #pragma unroll
         for (int a = 0; a < DIMV; ++a) {
@@ -632,7 +651,7 @@ __device__ __forceinline__ void moments_node(CDesc& cs, int x, int y, int z, boo
         }
     }
     const uint32_t na = n * (uint32_t)sizeof(CT);
-    *at_node<CT>(cs.phi, n) = phi;
+    *at_node<CT>(cs.phi[odd ? 1 : 0], n) = phi;
     const Slots<CT> Js = slots<CT>(cs.J, cs.N), Ms = slots<CT>(cs.M2, cs.N);
 #pragma unroll
     for (int a = 0; a < DIMV; ++a) *Js.at(a, na) = J[a];
@@ -697,7 +716,7 @@ __device__ __forceinline__ void pressure_tile(CDesc& cs, const TileCtx& t, doubl
     const int x = t.ox + lx, y = t.oy + ly, z = t.oz + lz;
     if (x >= cs.nx || y >= cs.ny || z >= cs.nz) return;
     const uint32_t n = (uint32_t)x + (uint32_t)cs.nx * ((uint32_t)y + (uint32_t)cs.ny * (uint32_t)z);
-    const double phi = (double)*at_node<AT>(cs.phi, n);
+    const double phi = (double)*at_node<AT>(cs.phi[t.step & 1], n);
     const double ra = cs.rho_a, rw = cs.rho_w;
     const double pc = phi < 0.0 ? 0.0 : (phi > 1.0 ? 1.0 : phi);
     const double rho = ra + pc * (rw - ra);
@@ -762,7 +781,7 @@ __device__ __forceinline__ void velocity_tile(CDesc& cs, const TileCtx& t, CT* s
     if (x >= cs.nx || y >= cs.ny || z >= cs.nz) return;
     const uint32_t n = (uint32_t)x + (uint32_t)cs.nx * ((uint32_t)y + (uint32_t)cs.ny * (uint32_t)z);
     const CT ra = (CT)cs.rho_a, dr = (CT)(cs.rho_w - cs.rho_a);
-    const CT rho = ra + clamp01(*at_node<CT>(cs.phi, n)) * dr;
+    const CT rho = ra + clamp01(*at_node<CT>(cs.phi[t.step & 1], n)) * dr;
     const CT irho = rcp(rho);
     const int cx = lx + 1, cy = ly + 1, cz = lz + HR::ZH;
     CT gr[3] = {0, 0, 0};
@@ -853,9 +872,11 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
     // own-node loads first
     S hraw[H::Q];
     CT m2[NM];
+    CT php = 0;  // reference of the incoming h (2-byte storage)
     if (inside) {
+        php = h_reference<S>(cs.phi[(t.step + 1) & 1], n);
 #pragma unroll
-        for (int j = 0; j < H::Q; ++j) hraw[j] = aa_load<H, WALL>(hs, nb, nv, j, odd);
+        for (int j = 0; j < H::Q; ++j) hraw[j] = aa_load<H, WALL, nt_access<S, kLoadCollide>()>(hs, nb, nv, j, odd);
         const Slots<CT> Ms = slots<CT>(cs.M2, cs.N);
 #pragma unroll
         for (int k = 0; k < NM; ++k) m2[k] = *Ms.at(k, na);
@@ -870,7 +891,7 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
         if (k >= R::N) break;
         int off[3], cr;
         const uint32_t m = HR::cell(cs, t, k, off, &cr);
-        const CT f = *at_node<CT>(cs.phi, m);
+        const CT f = *at_node<CT>(cs.phi[t.step & 1], m);
         sPhi[k] = f;
         sRho[k] = ph.rho_a + clamp01(f) * ph.drho;
 #pragma unroll
@@ -890,16 +911,27 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
     tile_gradients<DIMV, R, CT>(sPhi, sRho, sU, lx + 1, ly + 1, lz + HR::ZH, v);
     const NodeCoef<DIMV, CT> kc = node_coef<DIMV, false, CT>(ph, v, m2);
     const CT hisc = (CT)cs.h_inv_scale, hsc = (CT)cs.h_scale, gsc = (CT)cs.g_scale;
-    const CT phr = (CT)cs.phi_ref;
     const CT corr = (CT)6.0 * rcp(kc.rho);  // 2 / (rho T)
+    // reference of an outgoing h_j in 2-byte storage: w_j phi (this step) of
+    // the node that reads it next step -- x + c_j, or x itself for a
+    // population reflected at a wall
+    const int cx = lx + 1, cy = ly + 1, cz = lz + HR::ZH, c0 = R::idx(cx, cy, cz);
+    auto href = [&](int j, bool reflected) -> CT {
+        if constexpr (sizeof(S) != 2) {
+            return (CT)0;
+        } else {
+            const int k = reflected ? c0 : R::idx(cx + H::c(j, 0), cy + H::c(j, 1), cz + H::c(j, 2));
+            return (CT)H::w(j) * sPhi[k];
+        }
+    };
     // rest direction, then opposite pairs; both lattices share the direction
     // order, so h_i and g_i stream to the same node
     {
         const CT g0 = g_out<G, DIMV, false>(v, kc, 0);
-        aa_store<G, WALL>(gs, nb, nv, 0, odd, Codec<S>::enc(g0, gsc, (CT)0), false);
-        const CT h0 = Codec<S>::dec(sH[0][threadIdx.x], hisc, phr * (CT)H::w(0));
-        aa_store<H, WALL>(hs, nb, nv, 0, odd,
-                          Codec<S>::enc(h_out<H, DIMV, false>(ph, v, kc, 0, h0), hsc, phr * (CT)H::w(0)), false);
+        aa_store<G, WALL, nt_access<S, kStoreCollide>()>(gs, nb, nv, 0, odd, Codec<S>::enc(g0, gsc, (CT)0), false);
+        const CT h0 = Codec<S>::dec(sH[0][threadIdx.x], hisc, php * (CT)H::w(0));
+        aa_store<H, WALL, nt_access<S, kStoreCollide>()>(hs, nb, nv, 0, odd,
+                          Codec<S>::enc(h_out<H, DIMV, false>(ph, v, kc, 0, h0), hsc, href(0, true)), false);
     }
 #pragma unroll
     for (int i = 1; i < G::Q; i += 2) {
@@ -919,15 +951,16 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
             gi -= bi ? fc : (CT)0;
             gk += bk ? fc : (CT)0;
         }
-        aa_store<G, WALL>(gs, nb, nv, i, odd, Codec<S>::enc(gi, gsc, (CT)0), bi);
-        aa_store<G, WALL>(gs, nb, nv, i + 1, odd, Codec<S>::enc(gk, gsc, (CT)0), bk);
+        aa_store<G, WALL, nt_access<S, kStoreCollide>()>(gs, nb, nv, i, odd, Codec<S>::enc(gi, gsc, (CT)0), bi);
+        aa_store<G, WALL, nt_access<S, kStoreCollide>()>(gs, nb, nv, i + 1, odd, Codec<S>::enc(gk, gsc, (CT)0), bk);
         if (i < H::Q) {
-            const CT hi = Codec<S>::dec(sH[i][threadIdx.x], hisc, phr * (CT)H::w(i));
-            const CT hk = Codec<S>::dec(sH[i + 1][threadIdx.x], hisc, phr * (CT)H::w(i + 1));
+            const CT hi = Codec<S>::dec(sH[i][threadIdx.x], hisc, php * (CT)H::w(i));
+            const CT hk = Codec<S>::dec(sH[i + 1][threadIdx.x], hisc, php * (CT)H::w(i + 1));
             CT oi, ok;
             h_pair<H, DIMV, false>(ph, v, kc, i, hi, hk, &oi, &ok);
-            aa_store<H, WALL>(hs, nb, nv, i, odd, Codec<S>::enc(oi, hsc, phr * (CT)H::w(i)), bi);
-            aa_store<H, WALL>(hs, nb, nv, i + 1, odd, Codec<S>::enc(ok, hsc, phr * (CT)H::w(i + 1)), bk);
+            aa_store<H, WALL, nt_access<S, kStoreCollide>()>(hs, nb, nv, i, odd, Codec<S>::enc(oi, hsc, href(i, bi)), bi);
+            aa_store<H, WALL, nt_access<S, kStoreCollide>()>(hs, nb, nv, i + 1, odd,
+                                                             Codec<S>::enc(ok, hsc, href(i + 1, bk)), bk);
         }
     }
 }
@@ -996,13 +1029,16 @@ __global__ __launch_bounds__(256) void k_init(CaseTab cases, const int* tstart, 
     const NodeCoef<DIMV, CT> kc = node_coef<DIMV, true, CT>(ph, v, (const CT*)nullptr);
     const Slots<S> hs = slots<S>(cs.h, cs.N), gs = slots<S>(cs.g, cs.N);
     const uint32_t nb = n * (uint32_t)sizeof(S);
-    const CT hsc = (CT)cs.h_scale, gsc = (CT)cs.g_scale, phr = (CT)cs.phi_ref;
+    const CT hsc = (CT)cs.h_scale, gsc = (CT)cs.g_scale;
+    // 2-byte storage: h_j - w_j phi0 (the previous-step phi of step 0 is phi0)
+    const CT phr = sizeof(S) == 2 ? v.phi : (CT)0;
 #pragma unroll
     for (int j = 0; j < H::Q; ++j)
         *hs.at(j, nb) = Codec<S>::enc(h_out<H, DIMV, true>(ph, v, kc, j, (CT)0), hsc, phr * (CT)H::w(j));
 #pragma unroll
     for (int i = 0; i < G::Q; ++i) *gs.at(i, nb) = Codec<S>::enc(g_out<G, DIMV, true>(v, kc, i), gsc, (CT)0);
     *at_node<CT>(cs.P[0], n) = (CT)P0[n];
+    *at_node<CT>(cs.phi[1], n) = v.phi;
 }
 
 // --- step counters: every case of a table advances by k (up to its end).
@@ -1038,7 +1074,7 @@ __global__ __launch_bounds__(256) void k_diag(const CaseDev* __restrict__ csp, d
 {
     const CaseDev& cs = *csp;
     const int64_t N = cs.N;
-    const AT* phi = (const AT*)cs.phi;
+    const AT* phi = (const AT*)cs.phi[cs.step & 1];
     const AT* P = (const AT*)cs.P[(cs.step + 1) & 1];
     const AT* U = (const AT*)cs.U;
     double acc[kDiagVals] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};

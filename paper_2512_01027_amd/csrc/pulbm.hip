@@ -55,7 +55,7 @@ int store_bytes(int store) { return store == PULBM_STORE_FP64 ? 8 : store == PUL
 int aux_bytes(int store) { return store == PULBM_STORE_FP64 ? 8 : 4; }
 
 struct Layout {
-    size_t h, g, P0, P1, phi, J, S, M2, U, desc, tab, partial, diag, total;
+    size_t h, g, P0, P1, phi0, phi1, J, S, M2, U, desc, tab, partial, diag, total;
 };
 
 Layout make_layout(const pulbm_params& p)
@@ -70,7 +70,8 @@ Layout make_layout(const pulbm_params& p)
     L.g = put((size_t)p.q_hydro * N * sb);
     L.P0 = put(N * ab);
     L.P1 = put(N * ab);
-    L.phi = put(N * ab);
+    L.phi0 = put(N * ab);
+    L.phi1 = put(N * ab);
     L.J = put((size_t)dim * N * ab);
     L.S = put(N * ab);
     L.M2 = put((size_t)nm * N * ab);
@@ -93,8 +94,14 @@ int validate(const pulbm_params* p)
         return fail(PULBM_EINVAL, "2D cases use D2Q9 for both lattices (q_hydro = q_phase = 9)");
     if (p->dim == 3 && (p->q_hydro != 27 || p->q_phase != 19))
         return fail(PULBM_EINVAL, "3D cases use D3Q27 hydro + D3Q19 phase field (27, 19)");
-    if ((double)p->nx * p->ny * p->nz > 2.0e9) return fail(PULBM_EINVAL, "grid too large");
     if (p->store < PULBM_STORE_FP64 || p->store > PULBM_STORE_BF16) return fail(PULBM_EINVAL, "bad store %d", p->store);
+    // kernels address one field with 32-bit byte offsets (signed for the
+    // periodic neighbour steps): N times the widest element must stay below 2^31
+    const double nodes = (double)p->nx * p->ny * p->nz;
+    const int widest = std::max(store_bytes(p->store), aux_bytes(p->store));
+    if (nodes * widest >= 2147483648.0)
+        return fail(PULBM_EINVAL, "grid too large: %.0f nodes x %d bytes per field element must stay below 2^31",
+                    nodes, widest);
     if (p->reserved != 0) return fail(PULBM_EINVAL, "reserved field must be 0");
     for (int a = 0; a < 3; ++a)
         if (p->wall[a] != 0 && p->wall[a] != 1) return fail(PULBM_EINVAL, "wall[%d] must be 0 or 1", a);
@@ -197,17 +204,19 @@ void launch_init(int dim, int store, hipStream_t st, CaseDev* const* tab, const 
 #undef PULBM_INIT_CASE
 }
 
-// Codec constants: FP16 stores (h - w phi_ref) * 2^12 and g * 2^12; BF16 keeps
-// the FP32 exponent range (scale 1) with the same shift.
-void codec_constants(const pulbm_params& p, double phi_ref, CaseDev& h)
+// Codec constants.  FP16 stores h_j - w_j phi (phi of the reading node one
+// step earlier) times 2^14 and g times 2^12; the stored values are small
+// (|h_j - w_j phi| < w_j, |g_i| of the order of w_i |u| / T), so the scales
+// keep them in FP16's normal range without overflow.  BF16 has FP32's
+// exponent range and uses scale 1.
+void codec_constants(const pulbm_params& p, CaseDev& h)
 {
-    h.phi_ref = 0.0;
     h.h_scale = h.h_inv_scale = h.g_scale = h.g_inv_scale = 1.0;
-    if (p.store == PULBM_STORE_FP16 || p.store == PULBM_STORE_BF16) {
-        h.phi_ref = phi_ref;
-        const double s = p.store == PULBM_STORE_FP16 ? 4096.0 : 1.0;
-        h.h_scale = h.g_scale = s;
-        h.h_inv_scale = h.g_inv_scale = 1.0 / s;
+    if (p.store == PULBM_STORE_FP16) {
+        h.h_scale = 16384.0;
+        h.h_inv_scale = 1.0 / 16384.0;
+        h.g_scale = 4096.0;
+        h.g_inv_scale = 1.0 / 4096.0;
     }
 }
 
@@ -301,14 +310,15 @@ extern "C" int pulbm_create(const pulbm_params* p, void* dev_arena, size_t arena
     h.step_end = INT64_MAX;
     h.h = c->base + L.h; h.g = c->base + L.g;
     h.P[0] = c->base + L.P0; h.P[1] = c->base + L.P1;
-    h.phi = c->base + L.phi; h.J = c->base + L.J; h.S = c->base + L.S;
+    h.phi[0] = c->base + L.phi0; h.phi[1] = c->base + L.phi1;
+    h.J = c->base + L.J; h.S = c->base + L.S;
     h.M2 = c->base + L.M2; h.U = c->base + L.U;
     h.rho_a = p->rho_light; h.rho_w = p->rho_heavy;
     h.tau_a = p->nu_light / kT + 0.5;
     h.tau_w = p->nu_heavy / kT + 0.5;
     h.tau_phi = p->M / kT + 0.5;
     h.M = p->M; h.W = p->W; h.sigma = p->sigma; h.lambda_b = p->lambda_bulk;
-    codec_constants(*p, p->phi_ref >= 0 ? p->phi_ref : 0.0, h);
+    codec_constants(*p, h);
     c->d = (CaseDev*)(c->base + L.desc);
     c->tab = (CaseDev**)(c->base + L.tab);
     c->tstart = (int*)(c->base + L.tab + sizeof(CaseDev*));
@@ -339,16 +349,11 @@ extern "C" int pulbm_init_fields(pulbm_case* c, const double* phi, const double*
     if (!c || !phi || !P || !u) return fail(PULBM_EINVAL, "NULL argument");
     const size_t N = (size_t)c->h.N;
     const int dim = c->p.dim;
-    double mean = 0.0;
-    for (size_t n = 0; n < N; ++n) {
+    for (size_t n = 0; n < N; ++n)
         if (!std::isfinite(phi[n]) || !std::isfinite(P[n]))
             return fail(PULBM_EDIVERGED, "non-finite initial phi or P at node %zu", n);
-        mean += phi[n];
-    }
     for (size_t n = 0; n < (size_t)dim * N; ++n)
         if (!std::isfinite(u[n])) return fail(PULBM_EDIVERGED, "non-finite initial u at entry %zu", n);
-    mean /= (double)N;
-    if (c->p.phi_ref < 0) codec_constants(c->p, mean > 0.5 ? 1.0 : 0.0, c->h);
     c->h.step = 0;
     c->h.step_end = INT64_MAX;
     int rc = upload_desc(c);
@@ -436,7 +441,7 @@ extern "C" int pulbm_read_fields(pulbm_case* c, double* phi, double* P, double* 
     int rc = read_pass(c);
     if (rc) return rc;
     const size_t N = (size_t)c->h.N;
-    if ((rc = fetch(c, c->h.phi, phi, N))) return rc;
+    if ((rc = fetch(c, c->h.phi[c->step & 1], phi, N))) return rc;
     if ((rc = fetch(c, c->h.P[(c->step + 1) & 1], P, N))) return rc;
     if ((rc = fetch(c, c->h.U, u, (size_t)c->p.dim * N))) return rc;
     return PULBM_OK;
@@ -469,14 +474,15 @@ extern "C" int pulbm_diagnostics(pulbm_case* c, pulbm_diag* d)
     return PULBM_OK;
 }
 
-// Restart image: header, h, g, previous-step pressure.
+// Restart image: header, h, g, previous-step pressure, previous-step phi (the
+// reference of the 2-byte h codec).
 namespace {
+constexpr char kCkptMagic[9] = "PULBMCK2";
 struct CkptHeader {
     char magic[8];
     int32_t version, store;
     pulbm_params p;
     int64_t step;
-    double phi_ref;
     uint64_t h_bytes, g_bytes, P_bytes;
 };
 }  // namespace
@@ -485,7 +491,7 @@ extern "C" int pulbm_checkpoint_bytes(const pulbm_case* c, size_t* bytes)
 {
     if (!c || !bytes) return fail(PULBM_EINVAL, "NULL argument");
     const size_t N = (size_t)c->h.N, sb = store_bytes(c->p.store), ab = aux_bytes(c->p.store);
-    *bytes = sizeof(CkptHeader) + (size_t)(c->p.q_phase + c->p.q_hydro) * N * sb + N * ab;
+    *bytes = sizeof(CkptHeader) + (size_t)(c->p.q_phase + c->p.q_hydro) * N * sb + 2 * N * ab;
     return PULBM_OK;
 }
 
@@ -499,12 +505,11 @@ extern "C" int pulbm_checkpoint(pulbm_case* c, void* buf, size_t bytes)
     const size_t N = (size_t)c->h.N, sb = store_bytes(c->p.store), ab = aux_bytes(c->p.store);
     CkptHeader hd;
     std::memset(&hd, 0, sizeof hd);
-    std::memcpy(hd.magic, "PULBMCK1", 8);
-    hd.version = 1;
+    std::memcpy(hd.magic, kCkptMagic, 8);
+    hd.version = 2;
     hd.store = c->p.store;
     hd.p = c->p;
     hd.step = c->step;
-    hd.phi_ref = c->h.phi_ref;
     hd.h_bytes = (uint64_t)c->p.q_phase * N * sb;
     hd.g_bytes = (uint64_t)c->p.q_hydro * N * sb;
     hd.P_bytes = N * ab;
@@ -516,6 +521,8 @@ extern "C" int pulbm_checkpoint(pulbm_case* c, void* buf, size_t bytes)
     HIPC(hipMemcpyAsync(o, c->h.g, hd.g_bytes, hipMemcpyDeviceToHost, c->stream));
     o += hd.g_bytes;
     HIPC(hipMemcpyAsync(o, c->h.P[c->step & 1], hd.P_bytes, hipMemcpyDeviceToHost, c->stream));
+    o += hd.P_bytes;
+    HIPC(hipMemcpyAsync(o, c->h.phi[(c->step + 1) & 1], hd.P_bytes, hipMemcpyDeviceToHost, c->stream));
     HIPC(hipStreamSynchronize(c->stream));
     return PULBM_OK;
 }
@@ -526,7 +533,7 @@ extern "C" int pulbm_restore(pulbm_case* c, const void* buf, size_t bytes)
     if (bytes < sizeof(CkptHeader)) return fail(PULBM_EINVAL, "restart image too short");
     CkptHeader hd;
     std::memcpy(&hd, buf, sizeof hd);
-    if (std::memcmp(hd.magic, "PULBMCK1", 8) || hd.version != 1) return fail(PULBM_EINVAL, "not a restart image");
+    if (std::memcmp(hd.magic, kCkptMagic, 8) || hd.version != 2) return fail(PULBM_EINVAL, "not a restart image");
     const pulbm_params& q = hd.p;
     const pulbm_params& p = c->p;
     if (q.dim != p.dim || q.nx != p.nx || q.ny != p.ny || q.nz != p.nz || q.store != p.store ||
@@ -538,7 +545,6 @@ extern "C" int pulbm_restore(pulbm_case* c, const void* buf, size_t bytes)
     c->step = hd.step;
     c->h.step = hd.step;
     c->h.step_end = INT64_MAX;
-    c->h.phi_ref = hd.phi_ref;
     int rc = upload_desc(c);
     if (rc) return rc;
     const char* o = (const char*)buf + sizeof hd;
@@ -547,6 +553,8 @@ extern "C" int pulbm_restore(pulbm_case* c, const void* buf, size_t bytes)
     HIPC(hipMemcpyAsync(c->h.g, o, hd.g_bytes, hipMemcpyHostToDevice, c->stream));
     o += hd.g_bytes;
     HIPC(hipMemcpyAsync(c->h.P[c->step & 1], o, hd.P_bytes, hipMemcpyHostToDevice, c->stream));
+    o += hd.P_bytes;
+    HIPC(hipMemcpyAsync(c->h.phi[(c->step + 1) & 1], o, hd.P_bytes, hipMemcpyHostToDevice, c->stream));
     HIPC(hipStreamSynchronize(c->stream));
     c->ready = true;
     return PULBM_OK;

@@ -165,8 +165,9 @@ def test_fp32_matches_oracle(store, tol, case):
     _compare(g.read_fields(), o.read_fields(), tol, f"{case} {store}")
 
 
-def test_checkpoint_restart_bitwise():
-    cfg = W.base_case(3, 21, 9, 10, wall=(0, 0, 1), gravity=(0, 0, -1e-5), store="fp32")
+@pytest.mark.parametrize("store", ["fp32", "fp16"])
+def test_checkpoint_restart_bitwise(store):
+    cfg = W.base_case(3, 21, 9, 10, wall=(0, 0, 1), gravity=(0, 0, -1e-5), store=store)
     f = _fields(cfg)
     a = B.Case(cfg)
     a.init_fields(*f)

@@ -1,0 +1,110 @@
+"""Serving batch: many resident cases advanced together.
+
+- each case's result is bitwise the same alone (the single-case API), alone
+  in a batch and in a mix of 2D and 3D cases of other sizes and step counts,
+  including a case admitted while the others are part-way through;
+- each case runs exactly its requested number of steps, whatever the advance
+  granularity;
+- admission is bounded by the memory budget and the slot count (EAGAIN), and
+  a taken case frees both.
+"""
+import numpy as np
+import pytest
+
+from paper_2512_01027_amd import binding as B
+from paper_2512_01027_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _cases(store):
+    a = W.base_case(3, 24, 24, 24, sigma=0.005, nu_heavy=0.05, nu_light=0.05, store=store)
+    fa = W.droplet(a, 7.0, u0=(0.02, 0.01, 0.0))
+    b = W.base_case(2, 64, 48, wall=(0, 1, 0), gravity=(0.0, -1e-5, 0.0), sigma=0.01, nu_heavy=0.02,
+                    nu_light=0.2, W=5.0, store=store)
+    fb = W.droplet(b, 10.0, center=(32.0, 14.0, 0.0), heavy_inside=False)
+    c = W.base_case(3, 20, 16, 12, wall=(0, 0, 1), gravity=(0.0, 0.0, -1e-5), sigma=0.01, nu_heavy=0.02,
+                    nu_light=0.2, W=5.0, rho_heavy=100.0, store=store)
+    fc = W.droplet(c, 4.0, center=(10.0, 8.0, 4.0), heavy_inside=False)
+    d = W.base_case(2, 37, 29, store=store, rho_heavy=10.0)
+    fd = W.droplet(d, 8.0)
+    return [(a, fa, 37), (b, fb, 50), (c, fc, 23), (d, fd, 41)]
+
+
+def _alone(cfg, f, n):
+    c = B.Case(cfg)
+    c.init_fields(*f)
+    c.step(n)
+    out = c.read_fields()
+    c.close()
+    return out
+
+
+def _same(x, y):
+    return all(np.array_equal(a, b) for a, b in zip(x, y))
+
+
+@pytest.mark.parametrize("store", ["fp16", "fp32"])
+def test_alone_equals_mix_bitwise(store):
+    cases = _cases(store)
+    ref = [_alone(cfg, f, n) for cfg, f, n in cases]
+    bt = B.Batch(1 << 30, store=store, max_slots=8)
+    # the first three start together; the fourth arrives after 16 steps
+    slots = {}
+    for k in range(3):
+        cfg, f, n = cases[k]
+        slots[bt.admit(cfg, *f, n)] = k
+    got = {}
+    adv = 0
+    while len(got) < len(cases):
+        if adv == 16:
+            cfg, f, n = cases[3]
+            slots[bt.admit(cfg, *f, n)] = 3
+        bt.advance(8)
+        adv += 8
+        for s in bt.poll():
+            got[slots[s]] = bt.take(s)
+        assert adv < 200
+    for k in range(len(cases)):
+        assert _same(got[k], ref[k]), f"case {k} differs in the mix"
+    # a case alone in a batch, advanced one step at a time
+    cfg, f, n = cases[2]
+    s = bt.admit(cfg, *f, n)
+    for _ in range(n + 5):
+        bt.advance(1)
+    assert bt.poll() == [s]
+    assert _same(bt.take(s), ref[2])
+    assert bt.usage() == (0, 0)
+    bt.close()
+
+
+def test_admission_budget_and_slots():
+    cases = _cases("fp16")
+    cfg, f, n = cases[0]
+    probe = B.Batch(1 << 30, store="fp16", max_slots=4)
+    s0 = probe.admit(cfg, *f, n)
+    one, act = probe.usage()
+    assert act == 1 and one > 0
+    probe.close()
+    # budget for one case of this size only
+    bt = B.Batch(one + one // 2, store="fp16", max_slots=4)
+    s0 = bt.admit(cfg, *f, n)
+    assert s0 is not None
+    assert bt.admit(cfg, *f, n) is None  # EAGAIN: budget
+    bt.advance(n)
+    assert bt.poll() == [s0]
+    bt.take(s0)
+    assert bt.usage() == (0, 0)
+    assert bt.admit(cfg, *f, n) is not None  # room again
+    bt.close()
+    # slot limit
+    bt = B.Batch(1 << 30, store="fp16", max_slots=1)
+    assert bt.admit(cfg, *f, n) is not None
+    assert bt.admit(cfg, *f, n) is None
+    bt.close()
+    # a case of another store is rejected
+    bt = B.Batch(1 << 30, store="fp16", max_slots=2)
+    with pytest.raises(B.PulbmError) as e:
+        bt.admit(dict(cfg, store="fp32"), *f, n)
+    assert e.value.code == B.EINVAL
+    bt.close()
