@@ -113,27 +113,32 @@ def traffic_of(kernel_name, n):
     return None if k is None else int(round(k["read_bytes"] + k["write_bytes"]))
 
 
-def serving_leg(fp16_mlups, n_cases=64, step_scale=0.1):
+def serving_leg(n_cases=64, step_scale=0.1):
+    """Saturated burst (every request at t = 0: the capacity of each mode),
+    then a Poisson stream at 0.8 x the batched capacity."""
     import torch
 
     from paper_2512_01027_amd import serving as SV
 
     reqs = SV.make_stream(n_cases, "fp16", step_scale)
     mean_work = sum(r.work for r in reqs) / len(reqs)
-    rate = 0.8 * fp16_mlups * 1e6 / mean_work
     free, _ = torch.cuda.mem_get_info()
     budget = int(0.8 * free)
+    SV.set_arrivals(reqs, None)
+    burst_b = SV.run_batched(reqs, budget)
+    SV.set_arrivals(reqs, None)
+    burst_s = SV.run_sequential(reqs)
+    rate = 0.8 * burst_b["MLUPS"] * 1e6 / mean_work
     SV.set_arrivals(reqs, rate)
-    b = SV.run_batched(reqs, budget)
+    pois_b = SV.run_batched(reqs, budget)
     SV.set_arrivals(reqs, rate)
-    s = SV.run_sequential(reqs)
-    rep = SV.ServingReport(b, s).as_dict()
-    rep["sample"] = (f"{n_cases} requests (seed 3): 75% 3D n in [32,192], 25% 2D n in [128,1024] "
-                     f"(log-uniform), droplet / rising bubble, density ratio 10/100/1000, "
-                     f"steps U{{1000..10000}} x {step_scale}; Poisson arrivals (seed 2) at "
-                     f"{rate:.2f}/s = 0.8 x FP16 capacity / mean work; FP16 storage; "
-                     f"budget {budget / 2**30:.0f} GiB")
-    return rep
+    pois_s = SV.run_sequential(reqs)
+    return {"saturated": SV.compare(burst_b, burst_s), "poisson": SV.compare(pois_b, pois_s),
+            "sample": (f"{n_cases} requests (seed 3): 75% 3D n in [32,192], 25% 2D n in [128,1024] "
+                       f"(log-uniform), droplet / rising bubble, density ratio 10/100/1000, "
+                       f"steps U{{1000..10000}} x {step_scale}; FP16 storage; batch budget "
+                       f"{budget / 2**30:.0f} GiB; saturated: all at t=0; poisson: arrivals (seed 2) at "
+                       f"{rate:.2f}/s = 0.8 x batched capacity / mean work")}
 
 
 def cpu_baseline(cfg, fields):
@@ -220,7 +225,7 @@ def main():
                              "collide_GBs": round(kb16["collide"] * N / (ms16[3] * 1e-3) / 1e9, 1),
                              "effective_GBs": round(m16 * 1e6 * state_bytes(2) / 1e9, 1)}
         if not args.no_serving:
-            out["serving"] = serving_leg(m16)
+            out["serving"] = serving_leg()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, fields)
     print(json.dumps(out))

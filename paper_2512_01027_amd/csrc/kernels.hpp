@@ -69,8 +69,11 @@ using CDesc = const PULBM_CST CaseDev;
 
 template <class T> __device__ __forceinline__ PULBM_GLB T* glb(void* p) { return (PULBM_GLB T*)p; }
 
-// A launch covers the tiles of every case in a table of case pointers;
-// tstart[c] is the first tile of case c.
+// A launch covers the tiles of every case in a table of case pointers.  The
+// table's header lives in device memory next to it -- hdr[0] cases,
+// hdr[1] tiles in all, hdr[2 + c] the first tile of case c -- so a captured
+// graph stays valid while cases join and leave, as long as the grid has a
+// block for every tile.
 using CaseTab = CaseDev* const*;
 
 // --------------------------------------------------------------- launch map
@@ -108,14 +111,20 @@ struct TileCtx {
 };
 
 template <class Mo>
-__device__ __forceinline__ TileCtx tile_ctx(CaseTab cases, const int* tstart_, int ncases, int total_tiles,
-                                            int step_off)
+__device__ __forceinline__ TileCtx tile_ctx(CaseTab cases, const int* hdr_, int step_off)
 {
     TileCtx t;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const PULBM_CST int* hdr = (const PULBM_CST int*)hdr_;
+    const int ncases = hdr[0], total_tiles = hdr[1];
+    // the first blocks (a multiple of 8) take the tiles; the XCD remap runs
+    // over them only, so every XCD gets its share however large the grid
+    const int used = (total_tiles + 7) & ~7;
+    t.active = (int)blockIdx.x < used;
+    if (!t.active) return t;
+    const int tile = xcd_tile(blockIdx.x, used);
     t.active = tile < total_tiles;
     if (!t.active) return t;
-    const PULBM_CST int* tstart = (const PULBM_CST int*)tstart_;
+    const PULBM_CST int* tstart = hdr + 2;
     const int ci = find_case(tstart, ncases, tile);
     const PULBM_CST uint64_t* tab = (const PULBM_CST uint64_t*)(const void*)cases;
     t.cs = (CDesc*)(uintptr_t)tab[ci];
@@ -662,11 +671,10 @@ __device__ __forceinline__ void moments_node(CDesc& cs, int x, int y, int z, boo
 }
 
 template <int DIMV, class S>
-__global__ __launch_bounds__(256) void k_moments(CaseTab cases, const int* tstart, int ncases, int total_tiles,
-                                                 int step_off)
+__global__ __launch_bounds__(256) void k_moments(CaseTab cases, const int* hdr, int step_off)
 {
     using Mo = Model<DIMV>;
-    const TileCtx t = tile_ctx<Mo>(cases, tstart, ncases, total_tiles, step_off);
+    const TileCtx t = tile_ctx<Mo>(cases, hdr, step_off);
     if (!t.active) return;
     CDesc& cs = *t.cs;
     int lx, ly, lz;
@@ -742,13 +750,12 @@ __device__ __forceinline__ void pressure_tile(CDesc& cs, const TileCtx& t, doubl
 }
 
 template <int DIMV, class AT>
-__global__ __launch_bounds__(256) void k_pressure(CaseTab cases, const int* tstart, int ncases,
-                                                  int total_tiles, int step_off)
+__global__ __launch_bounds__(256) void k_pressure(CaseTab cases, const int* hdr, int step_off)
 {
     using Mo = Model<DIMV>;
     using R = typename Halo1<Mo, DIMV>::R;
     __shared__ double sP[R::N], sGD[R::N], sJ[DIMV][R::N];
-    const TileCtx t = tile_ctx<Mo>(cases, tstart, ncases, total_tiles, step_off);
+    const TileCtx t = tile_ctx<Mo>(cases, hdr, step_off);
     if (!t.active) return;
     CDesc& cs = *t.cs;
     if (tile_at_wall<Mo>(cs, t.ox, t.oy, t.oz)) pressure_tile<DIMV, AT, true, R>(cs, t, sP, sGD, sJ);
@@ -803,13 +810,12 @@ __device__ __forceinline__ void velocity_tile(CDesc& cs, const TileCtx& t, CT* s
 }
 
 template <int DIMV, class CT>
-__global__ __launch_bounds__(256) void k_velocity(CaseTab cases, const int* tstart, int ncases,
-                                                  int total_tiles, int step_off)
+__global__ __launch_bounds__(256) void k_velocity(CaseTab cases, const int* hdr, int step_off)
 {
     using Mo = Model<DIMV>;
     using R = typename Halo1<Mo, DIMV>::R;
     __shared__ CT sP[R::N], sGD[R::N];
-    const TileCtx t = tile_ctx<Mo>(cases, tstart, ncases, total_tiles, step_off);
+    const TileCtx t = tile_ctx<Mo>(cases, hdr, step_off);
     if (!t.active) return;
     CDesc& cs = *t.cs;
     if (tile_at_wall<Mo>(cs, t.ox, t.oy, t.oz)) velocity_tile<DIMV, CT, true, R>(cs, t, sP, sGD);
@@ -966,8 +972,7 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
 }
 
 template <int DIMV, class S>
-__global__ __launch_bounds__(256) void k_collide(CaseTab cases, const int* tstart, int ncases, int total_tiles,
-                                                 int step_off)
+__global__ __launch_bounds__(256) void k_collide(CaseTab cases, const int* hdr, int step_off)
 {
     using Mo = Model<DIMV>;
     using H = typename Mo::H;
@@ -975,7 +980,7 @@ __global__ __launch_bounds__(256) void k_collide(CaseTab cases, const int* tstar
     using R = typename Halo1<Mo, DIMV>::R;
     __shared__ CT sPhi[R::N], sRho[R::N], sU[DIMV][R::N];
     __shared__ S sH[H::Q][256];
-    const TileCtx t = tile_ctx<Mo>(cases, tstart, ncases, total_tiles, step_off);
+    const TileCtx t = tile_ctx<Mo>(cases, hdr, step_off);
     if (!t.active) return;
     CDesc& cs = *t.cs;
     if (tile_at_wall<Mo>(cs, t.ox, t.oy, t.oz)) collide_tile<DIMV, S, true, R>(cs, t, sPhi, sRho, sU, sH);
@@ -985,7 +990,7 @@ __global__ __launch_bounds__(256) void k_collide(CaseTab cases, const int* tstar
 // --- initial state: equilibria of (phi0, P0, u0) in the even AA layout,
 //     previous-step pressure P[0] = P0.  Inputs are FP64 device arrays.
 template <int DIMV, class S>
-__global__ __launch_bounds__(256) void k_init(CaseTab cases, const int* tstart, int ncases, int total_tiles,
+__global__ __launch_bounds__(256) void k_init(CaseTab cases, const int* hdr,
                                               const double* __restrict__ phi0, const double* __restrict__ P0,
                                               const double* __restrict__ u0)
 {
@@ -996,7 +1001,7 @@ __global__ __launch_bounds__(256) void k_init(CaseTab cases, const int* tstart, 
     using HR = Halo1<Mo, DIMV>;
     using R = typename HR::R;
     __shared__ CT sPhi[R::N], sRho[R::N], sU[DIMV][R::N];
-    const TileCtx t = tile_ctx<Mo>(cases, tstart, ncases, total_tiles, 0);
+    const TileCtx t = tile_ctx<Mo>(cases, hdr, 0);
     if (!t.active) return;
     CDesc& cs = *t.cs;
     const uint32_t N = (uint32_t)cs.N;
@@ -1042,10 +1047,10 @@ __global__ __launch_bounds__(256) void k_init(CaseTab cases, const int* tstart, 
 }
 
 // --- step counters: every case of a table advances by k (up to its end).
-__global__ void k_advance(CaseTab cases, int ncases, int k)
+__global__ void k_advance(CaseTab cases, const int* hdr, int k)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncases) return;
+    if (c >= hdr[0]) return;
     CaseDev* cs = cases[c];
     const int64_t s = cs->step + k;
     cs->step = s < cs->step_end ? s : cs->step_end;

@@ -77,7 +77,7 @@ Layout make_layout(const pulbm_params& p)
     L.M2 = put((size_t)nm * N * ab);
     L.U = put((size_t)dim * N * ab);
     L.desc = put(sizeof(CaseDev));
-    L.tab = put(sizeof(CaseDev*) + 2 * sizeof(int));
+    L.tab = put(sizeof(CaseDev*) + 4 * sizeof(int));
     L.partial = put((size_t)kDiagBlocks * kDiagVals * sizeof(double));
     L.diag = put(kDiagVals * sizeof(double));
     L.total = o;
@@ -141,7 +141,7 @@ struct pulbm_case {
     CaseDev h;          // host copy of the descriptor
     CaseDev* d = nullptr;
     CaseDev** tab = nullptr;  // device {d}
-    int* tstart = nullptr;    // device {0, ntiles}
+    int* hdr = nullptr;       // device tile table header {1, ntiles, 0, ntiles}
     int ntiles = 0;
     int64_t step = 0;
     bool ready = false;
@@ -152,53 +152,52 @@ struct pulbm_case {
 namespace {
 
 template <int DIMV, class S>
-void launch_step(hipStream_t st, CaseDev* const* tab, const int* tstart, int ncases, int tiles, int off,
-                 int which)
+void launch_step(hipStream_t st, CaseDev* const* tab, const int* hdr, int blocks, int off, int which)
 {
     using CT = typename Codec<S>::CT;
-    const dim3 grid(grid_of(tiles)), block(256);
-    if (which == 0) hipLaunchKernelGGL((k_moments<DIMV, S>), grid, block, 0, st, tab, tstart, ncases, tiles, off);
-    if (which == 1) hipLaunchKernelGGL((k_pressure<DIMV, CT>), grid, block, 0, st, tab, tstart, ncases, tiles, off);
-    if (which == 2) hipLaunchKernelGGL((k_velocity<DIMV, CT>), grid, block, 0, st, tab, tstart, ncases, tiles, off);
-    if (which == 3) hipLaunchKernelGGL((k_collide<DIMV, S>), grid, block, 0, st, tab, tstart, ncases, tiles, off);
+    const dim3 grid(blocks), block(256);
+    if (which == 0) hipLaunchKernelGGL((k_moments<DIMV, S>), grid, block, 0, st, tab, hdr, off);
+    if (which == 1) hipLaunchKernelGGL((k_pressure<DIMV, CT>), grid, block, 0, st, tab, hdr, off);
+    if (which == 2) hipLaunchKernelGGL((k_velocity<DIMV, CT>), grid, block, 0, st, tab, hdr, off);
+    if (which == 3) hipLaunchKernelGGL((k_collide<DIMV, S>), grid, block, 0, st, tab, hdr, off);
 }
 
 template <int DIMV>
-void launch_dim(int store, hipStream_t st, CaseDev* const* tab, const int* tstart, int ncases, int tiles,
-                int off, int which)
+void launch_dim(int store, hipStream_t st, CaseDev* const* tab, const int* hdr, int blocks, int off, int which)
 {
     switch (store) {
-        case PULBM_STORE_FP64: launch_step<DIMV, double>(st, tab, tstart, ncases, tiles, off, which); break;
-        case PULBM_STORE_FP32: launch_step<DIMV, float>(st, tab, tstart, ncases, tiles, off, which); break;
-        case PULBM_STORE_FP16: launch_step<DIMV, _Float16>(st, tab, tstart, ncases, tiles, off, which); break;
-        default: launch_step<DIMV, uint16_t>(st, tab, tstart, ncases, tiles, off, which); break;
+        case PULBM_STORE_FP64: launch_step<DIMV, double>(st, tab, hdr, blocks, off, which); break;
+        case PULBM_STORE_FP32: launch_step<DIMV, float>(st, tab, hdr, blocks, off, which); break;
+        case PULBM_STORE_FP16: launch_step<DIMV, _Float16>(st, tab, hdr, blocks, off, which); break;
+        default: launch_step<DIMV, uint16_t>(st, tab, hdr, blocks, off, which); break;
     }
 }
 
-// which: 0 moments, 1 pressure, 2 velocity, 3 collide + stream
-void launch(int dim, int store, hipStream_t st, CaseDev* const* tab, const int* tstart, int ncases, int tiles,
-            int off, int which)
+// which: 0 moments, 1 pressure, 2 velocity, 3 collide + stream.  blocks must
+// cover the table's tiles (rounded up to a multiple of 8); extra blocks exit.
+void launch(int dim, int store, hipStream_t st, CaseDev* const* tab, const int* hdr, int blocks, int off,
+            int which)
 {
-    if (dim == 2) launch_dim<2>(store, st, tab, tstart, ncases, tiles, off, which);
-    else launch_dim<3>(store, st, tab, tstart, ncases, tiles, off, which);
+    if (dim == 2) launch_dim<2>(store, st, tab, hdr, blocks, off, which);
+    else launch_dim<3>(store, st, tab, hdr, blocks, off, which);
 }
 
 template <int DIMV, class S>
-void launch_init_t(hipStream_t st, CaseDev* const* tab, const int* tstart, int tiles, const double* phi,
+void launch_init_t(hipStream_t st, CaseDev* const* tab, const int* hdr, int blocks, const double* phi,
                    const double* P, const double* u)
 {
-    hipLaunchKernelGGL((k_init<DIMV, S>), dim3(grid_of(tiles)), dim3(256), 0, st, tab, tstart, 1, tiles, phi, P, u);
+    hipLaunchKernelGGL((k_init<DIMV, S>), dim3(blocks), dim3(256), 0, st, tab, hdr, phi, P, u);
 }
 
-void launch_init(int dim, int store, hipStream_t st, CaseDev* const* tab, const int* tstart, int tiles,
+void launch_init(int dim, int store, hipStream_t st, CaseDev* const* tab, const int* hdr, int blocks,
                  const double* phi, const double* P, const double* u)
 {
 #define PULBM_INIT_CASE(D)                                                                          \
     switch (store) {                                                                                \
-        case PULBM_STORE_FP64: launch_init_t<D, double>(st, tab, tstart, tiles, phi, P, u); break;  \
-        case PULBM_STORE_FP32: launch_init_t<D, float>(st, tab, tstart, tiles, phi, P, u); break;   \
-        case PULBM_STORE_FP16: launch_init_t<D, _Float16>(st, tab, tstart, tiles, phi, P, u); break;\
-        default: launch_init_t<D, uint16_t>(st, tab, tstart, tiles, phi, P, u); break;                \
+        case PULBM_STORE_FP64: launch_init_t<D, double>(st, tab, hdr, blocks, phi, P, u); break;    \
+        case PULBM_STORE_FP32: launch_init_t<D, float>(st, tab, hdr, blocks, phi, P, u); break;     \
+        case PULBM_STORE_FP16: launch_init_t<D, _Float16>(st, tab, hdr, blocks, phi, P, u); break;  \
+        default: launch_init_t<D, uint16_t>(st, tab, hdr, blocks, phi, P, u); break;                \
     }
     if (dim == 2) { PULBM_INIT_CASE(2) } else { PULBM_INIT_CASE(3) }
 #undef PULBM_INIT_CASE
@@ -228,7 +227,8 @@ int upload_desc(pulbm_case* c)
 
 int read_pass(pulbm_case* c)
 {
-    for (int w = 0; w < kReadKernels; ++w) launch(c->p.dim, c->p.store, c->stream, c->tab, c->tstart, 1, c->ntiles, 0, w);
+    for (int w = 0; w < kReadKernels; ++w)
+        launch(c->p.dim, c->p.store, c->stream, c->tab, c->hdr, grid_of(c->ntiles), 0, w);
     HIPC(hipGetLastError());
     return PULBM_OK;
 }
@@ -321,10 +321,9 @@ extern "C" int pulbm_create(const pulbm_params* p, void* dev_arena, size_t arena
     codec_constants(*p, h);
     c->d = (CaseDev*)(c->base + L.desc);
     c->tab = (CaseDev**)(c->base + L.tab);
-    c->tstart = (int*)(c->base + L.tab + sizeof(CaseDev*));
-    struct { CaseDev* d; int ts[2]; } tabh = {c->d, {0, c->ntiles}};
-    hipError_t e = hipMemcpyAsync(c->tab, &tabh, sizeof(CaseDev*) + 2 * sizeof(int), hipMemcpyHostToDevice,
-                                  c->stream);
+    c->hdr = (int*)(c->base + L.tab + sizeof(CaseDev*));
+    struct { CaseDev* d; int hdr[4]; } tabh = {c->d, {1, c->ntiles, 0, c->ntiles}};
+    hipError_t e = hipMemcpyAsync(c->tab, &tabh, sizeof tabh, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(c->d, &c->h, sizeof(CaseDev), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
@@ -358,19 +357,25 @@ extern "C" int pulbm_init_fields(pulbm_case* c, const double* phi, const double*
     c->h.step_end = INT64_MAX;
     int rc = upload_desc(c);
     if (rc) return rc;
-    double* tmp = nullptr;
+    // stage the FP64 inputs in the case's own scratch fields (u*, S, M2, u),
+    // which k_init does not touch; no allocation on this path
     const size_t bytes = (2 + (size_t)dim) * N * sizeof(double);
-    HIPC(hipMalloc((void**)&tmp, bytes));
+    double* tmp = (double*)(c->base + c->L.J);
+    bool own_tmp = false;
+    if (bytes > c->L.desc - c->L.J) {
+        HIPC(hipMalloc((void**)&tmp, bytes));
+        own_tmp = true;
+    }
     hipError_t e = hipMemcpyAsync(tmp, phi, N * sizeof(double), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(tmp + N, P, N * sizeof(double), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(tmp + 2 * N, u, (size_t)dim * N * sizeof(double), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) {
-        launch_init(dim, c->p.store, c->stream, c->tab, c->tstart, c->ntiles, tmp, tmp + N, tmp + 2 * N);
+        launch_init(dim, c->p.store, c->stream, c->tab, c->hdr, grid_of(c->ntiles), tmp, tmp + N, tmp + 2 * N);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    (void)hipFree(tmp);
+    if (own_tmp) (void)hipFree(tmp);
     if (e != hipSuccess) return fail(PULBM_EDEVICE, "init failed: %s", hipGetErrorString(e));
     c->step = 0;
     c->ready = true;
@@ -383,8 +388,8 @@ static int queue_steps(pulbm_case* c, int64_t nsteps)
         const int chunk = (int)std::min<int64_t>(nsteps - s, 1 << 20);
         for (int k = 0; k < chunk; ++k)
             for (int w = 0; w < kStepKernels; ++w)
-                launch(c->p.dim, c->p.store, c->stream, c->tab, c->tstart, 1, c->ntiles, k, w);
-        hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, c->stream, c->tab, 1, chunk);
+                launch(c->p.dim, c->p.store, c->stream, c->tab, c->hdr, grid_of(c->ntiles), k, w);
+        hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, c->stream, c->tab, c->hdr, chunk);
         HIPC(hipGetLastError());
         s += chunk;
     }
@@ -411,10 +416,10 @@ extern "C" int pulbm_step_timed(pulbm_case* c, int64_t nsteps, double* ms)
     for (int64_t s = 0; s < nsteps && rc == PULBM_OK; ++s) {
         (void)hipEventRecord(ev[0], c->stream);
         for (int w = 0; w < kStepKernels; ++w) {
-            launch(c->p.dim, c->p.store, c->stream, c->tab, c->tstart, 1, c->ntiles, 0, w);
+            launch(c->p.dim, c->p.store, c->stream, c->tab, c->hdr, grid_of(c->ntiles), 0, w);
             (void)hipEventRecord(ev[w + 1], c->stream);
         }
-        hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, c->stream, c->tab, 1, 1);
+        hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, c->stream, c->tab, c->hdr, 1);
         hipError_t e = hipGetLastError();
         if (e == hipSuccess) e = hipEventSynchronize(ev[kStepKernels]);
         if (e != hipSuccess) {
@@ -576,23 +581,57 @@ struct pulbm_batch {
     int store = 0, max_slots = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    // one device arena of the whole budget; cases are carved from it
+    // (first fit, 256-byte granules, neighbouring holes merged on release)
+    char* arena = nullptr;
+    std::map<size_t, size_t> holes;  // offset -> bytes
     struct Slot {
         pulbm_case* c = nullptr;
         int64_t end = 0;
-        size_t bytes = 0;
+        size_t bytes = 0, off = 0;
     };
     std::vector<Slot> slots;
-    // per lattice dimension: device table of case pointers + tile starts
+    // per lattice dimension: device table of case pointers + its header
     struct Tab {
         CaseDev** dtab = nullptr;
-        int* dts = nullptr;
-        int cap = 0, ncases = 0, tiles = 0;
-        std::map<int, hipGraphExec_t> graphs;  // by ksteps
+        int* dhdr = nullptr;  // {ncases, tiles, tstart[0..ncases]}
+        int cap = 0, ncases = 0, tiles = 0, grid = 0;
+        std::map<int, hipGraphExec_t> graphs;  // by ksteps, captured for `grid` blocks
     } tab[2];
     bool dirty = true;
 };
 
 namespace {
+
+bool arena_take(pulbm_batch* b, size_t bytes, size_t* off)
+{
+    for (auto it = b->holes.begin(); it != b->holes.end(); ++it) {
+        if (it->second < bytes) continue;
+        *off = it->first;
+        const size_t rest = it->second - bytes;
+        b->holes.erase(it);
+        if (rest) b->holes[*off + bytes] = rest;
+        return true;
+    }
+    return false;
+}
+
+void arena_give(pulbm_batch* b, size_t off, size_t bytes)
+{
+    auto it = b->holes.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != b->holes.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        b->holes.erase(nx);
+    }
+    if (it != b->holes.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+            pv->second += it->second;
+            b->holes.erase(it);
+        }
+    }
+}
 
 void drop_graphs(pulbm_batch::Tab& t)
 {
@@ -606,28 +645,38 @@ int rebuild_tables(pulbm_batch* b)
     for (int di = 0; di < 2; ++di) {
         const int dim = di + 2;
         pulbm_batch::Tab& t = b->tab[di];
-        drop_graphs(t);
         std::vector<CaseDev*> ptr;
-        std::vector<int> ts{0};
+        std::vector<int> hdr{0, 0, 0};
         for (auto& s : b->slots)
             if (s.c && s.c->p.dim == dim) {
                 ptr.push_back(s.c->d);
-                ts.push_back(ts.back() + s.c->ntiles);
+                hdr.push_back(hdr.back() + s.c->ntiles);
             }
         t.ncases = (int)ptr.size();
-        t.tiles = ts.back();
+        t.tiles = hdr.back();
+        hdr[0] = t.ncases;
+        hdr[1] = t.tiles;
         if (t.ncases == 0) continue;
         if (t.cap < t.ncases) {
+            drop_graphs(t);
             if (t.dtab) (void)hipFree(t.dtab);
-            if (t.dts) (void)hipFree(t.dts);
+            if (t.dhdr) (void)hipFree(t.dhdr);
             t.dtab = nullptr;
-            t.dts = nullptr;
+            t.dhdr = nullptr;
             t.cap = std::max(t.ncases, b->max_slots);
             HIPC(hipMalloc((void**)&t.dtab, t.cap * sizeof(CaseDev*)));
-            HIPC(hipMalloc((void**)&t.dts, (t.cap + 1) * sizeof(int)));
+            HIPC(hipMalloc((void**)&t.dhdr, (t.cap + 3) * sizeof(int)));
+        }
+        // every block of a launch that finds no tile still costs a dispatch,
+        // so the captured grid follows the tile count: recapture when it no
+        // longer covers the tiles or exceeds them by more than a quarter
+        const int g = grid_of(t.tiles);
+        if (g > t.grid || 4 * t.grid > 5 * g) {
+            drop_graphs(t);
+            t.grid = g;
         }
         HIPC(hipMemcpyAsync(t.dtab, ptr.data(), t.ncases * sizeof(CaseDev*), hipMemcpyHostToDevice, b->stream));
-        HIPC(hipMemcpyAsync(t.dts, ts.data(), (t.ncases + 1) * sizeof(int), hipMemcpyHostToDevice, b->stream));
+        HIPC(hipMemcpyAsync(t.dhdr, hdr.data(), hdr.size() * sizeof(int), hipMemcpyHostToDevice, b->stream));
     }
     HIPC(hipStreamSynchronize(b->stream));
     b->dirty = false;
@@ -648,10 +697,19 @@ extern "C" int pulbm_batch_create(size_t budget, int32_t store, int32_t max_slot
     b->budget = budget;
     b->store = store;
     b->max_slots = max_slots;
+    if (budget) {
+        hipError_t e = hipMalloc((void**)&b->arena, budget);
+        if (e != hipSuccess) {
+            delete b;
+            return fail(PULBM_ENOMEM, "batch arena of %zu bytes: %s", budget, hipGetErrorString(e));
+        }
+        b->holes[0] = budget;
+    }
     b->stream = (hipStream_t)hip_stream;
     if (!b->stream) {  // graph capture needs a stream other than the null stream
         hipError_t e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
         if (e != hipSuccess) {
+            if (b->arena) (void)hipFree(b->arena);
             delete b;
             return fail(PULBM_EDEVICE, "hipStreamCreate failed: %s", hipGetErrorString(e));
         }
@@ -670,26 +728,33 @@ extern "C" int pulbm_batch_admit(pulbm_batch* b, const pulbm_params* p, const do
     if (rc) return rc;
     if (p->store != b->store) return fail(PULBM_EINVAL, "case store %d differs from the batch's %d", p->store, b->store);
     if (nsteps < 0) return fail(PULBM_EINVAL, "nsteps < 0");
-    const size_t bytes = make_layout(*p).total;
+    const size_t bytes = align_up(make_layout(*p).total);
     int free_slot = -1;
     for (int i = 0; i < b->max_slots; ++i)
         if (!b->slots[i].c) { free_slot = i; break; }
     if (free_slot < 0) return fail(PULBM_EAGAIN, "no free slot");
-    if (b->used + bytes > b->budget) return fail(PULBM_EAGAIN, "needs %zu bytes, %zu of %zu free", bytes, b->budget - b->used, b->budget);
+    size_t off = 0;
+    if (b->used + bytes > b->budget || !arena_take(b, bytes, &off))
+        return fail(PULBM_EAGAIN, "needs %zu bytes, %zu of %zu free", bytes, b->budget - b->used, b->budget);
     pulbm_case* c = nullptr;
-    if ((rc = pulbm_create(p, nullptr, 0, b->stream, &c))) return rc;
-    if ((rc = pulbm_init_fields(c, phi, P, u))) {
-        pulbm_destroy(c);
+    if ((rc = pulbm_create(p, b->arena + off, bytes, b->stream, &c))) {
+        arena_give(b, off, bytes);
         return rc;
     }
-    c->h.step_end = nsteps;
-    if ((rc = upload_desc(c))) {
+    if (!rc) rc = pulbm_init_fields(c, phi, P, u);
+    if (!rc) {
+        c->h.step_end = nsteps;
+        rc = upload_desc(c);
+    }
+    if (rc) {
         pulbm_destroy(c);
+        arena_give(b, off, bytes);
         return rc;
     }
     b->slots[free_slot].c = c;
     b->slots[free_slot].end = nsteps;
     b->slots[free_slot].bytes = bytes;
+    b->slots[free_slot].off = off;
     b->used += bytes;
     b->dirty = true;
     *slot = free_slot;
@@ -714,8 +779,8 @@ extern "C" int pulbm_batch_advance(pulbm_batch* b, int32_t ksteps)
             HIPC(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
             for (int k = 0; k < ksteps; ++k)
                 for (int w = 0; w < kStepKernels; ++w)
-                    launch(di + 2, b->store, b->stream, t.dtab, t.dts, t.ncases, t.tiles, k, w);
-            hipLaunchKernelGGL(k_advance, dim3((t.ncases + 63) / 64), dim3(64), 0, b->stream, t.dtab, t.ncases, ksteps);
+                    launch(di + 2, b->store, b->stream, t.dtab, t.dhdr, t.grid, k, w);
+            hipLaunchKernelGGL(k_advance, dim3((t.cap + 63) / 64), dim3(64), 0, b->stream, t.dtab, t.dhdr, ksteps);
             HIPC(hipStreamEndCapture(b->stream, &g));
             HIPC(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
             (void)hipGraphDestroy(g);
@@ -758,6 +823,7 @@ extern "C" int pulbm_batch_take(pulbm_batch* b, int32_t slot, double* phi, doubl
     rc = pulbm_read_fields(s.c, phi, P, u);
     if (rc) return rc;
     pulbm_destroy(s.c);
+    arena_give(b, s.off, s.bytes);
     b->used -= s.bytes;
     s = pulbm_batch::Slot();
     b->dirty = true;
@@ -785,8 +851,9 @@ extern "C" void pulbm_batch_destroy(pulbm_batch* b)
     for (auto& t : b->tab) {
         drop_graphs(t);
         if (t.dtab) (void)hipFree(t.dtab);
-        if (t.dts) (void)hipFree(t.dts);
+        if (t.dhdr) (void)hipFree(t.dhdr);
     }
+    if (b->arena) (void)hipFree(b->arena);
     if (b->own_stream) (void)hipStreamDestroy(b->stream);
     delete b;
 }

@@ -15,7 +15,7 @@ from __future__ import annotations
 
 import math
 import time
-from dataclasses import dataclass, field
+from dataclasses import dataclass
 
 import numpy as np
 
@@ -54,9 +54,13 @@ def make_stream(n_cases: int, store: str = "fp16", step_scale: float = 0.1, case
     return out
 
 
-def set_arrivals(reqs, rate_per_s: float, seed: int = 2):
-    rng = np.random.Generator(np.random.PCG64(seed))
-    t = np.cumsum(rng.exponential(1.0 / rate_per_s, size=len(reqs)))
+def set_arrivals(reqs, rate_per_s: float | None, seed: int = 2):
+    """Poisson arrivals at rate_per_s; None: every request arrives at once."""
+    if rate_per_s is None:
+        t = np.zeros(len(reqs))
+    else:
+        rng = np.random.Generator(np.random.PCG64(seed))
+        t = np.cumsum(rng.exponential(1.0 / rate_per_s, size=len(reqs)))
     for r, a in zip(reqs, t):
         r.arrival = float(a)
         r.done = math.nan
@@ -130,13 +134,7 @@ def run_sequential(reqs):
     return _summary(reqs, makespan)
 
 
-@dataclass
-class ServingReport:
-    batched: dict = field(default_factory=dict)
-    sequential: dict = field(default_factory=dict)
-
-    def as_dict(self):
-        b, s = self.batched, self.sequential
-        return {"batched": b, "sequential": s,
-                "throughput_ratio": round(b["MLUPS"] / s["MLUPS"], 3) if s else None,
-                "p99_ratio": round(b["latency_p99_s"] / s["latency_p99_s"], 3) if s else None}
+def compare(batched: dict, sequential: dict) -> dict:
+    return {"batched": batched, "sequential": sequential,
+            "throughput_ratio": round(batched["MLUPS"] / sequential["MLUPS"], 3),
+            "p99_ratio": round(batched["latency_p99_s"] / sequential["latency_p99_s"], 3)}
