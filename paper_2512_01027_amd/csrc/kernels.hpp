@@ -688,11 +688,10 @@ __global__ __launch_bounds__(256) void k_moments(CaseTab cases, const int* hdr, 
 
 // --- pressure (Sec. II): P = rho_ref T sum_i (g_i + (1 + omega) K_i)
 //     + omega rho_ref sum_i w_i c_i . u*(x - c_i), K_i from the previous
-//     pressure.  FP64 arithmetic whatever the storage precision (values are
-//     widened once, when the tile is staged in LDS).
+//     pressure.  FP64 arithmetic whatever the storage precision; the tile is
+//     staged in LDS in the storage type (exact) and widened at use.
 template <int DIMV, class AT, bool WALL, class R>
-__device__ __forceinline__ void pressure_tile(CDesc& cs, const TileCtx& t, double* sP, double* sGD,
-                                              double (*sJ)[R::N])
+__device__ __forceinline__ void pressure_tile(CDesc& cs, const TileCtx& t, AT* sP, AT* sGD, AT (*sJ)[R::N])
 {
     using Mo = Model<DIMV>;
     using G = typename Mo::G;
@@ -707,14 +706,14 @@ __device__ __forceinline__ void pressure_tile(CDesc& cs, const TileCtx& t, doubl
         if (k >= R::N) break;
         int off[3], cr;
         const uint32_t m = HR::cell(cs, t, k, off, &cr);
-        sP[k] = (double)*at_node<AT>(Pl, m);
+        sP[k] = *at_node<AT>(Pl, m);
         // ghost pressure = P(mirror) + rho(x) g.(ghost - mirror): keep g.off
-        if (WALL) sGD[k] = cs.grav[0] * off[0] + cs.grav[1] * off[1] + cs.grav[2] * off[2];
+        if (WALL) sGD[k] = (AT)(cs.grav[0] * off[0] + cs.grav[1] * off[1] + cs.grav[2] * off[2]);
 #pragma unroll
         for (int a = 0; a < DIMV; ++a) {
-            double j = (double)*Js.at(a, m * (uint32_t)sizeof(AT));
+            AT j = *Js.at(a, m * (uint32_t)sizeof(AT));
             // u* at a ghost: flow part odd, body-force part even
-            if (WALL && (cr & 1)) j = -j + 2.0 * cs.grav[a];
+            if (WALL && (cr & 1)) j = (AT)(-(double)j + 2.0 * cs.grav[a]);
             sJ[a][k] = j;
         }
     }
@@ -730,17 +729,17 @@ __device__ __forceinline__ void pressure_tile(CDesc& cs, const TileCtx& t, doubl
     const double rho = ra + pc * (rw - ra);
     const double omega = (rho - ra) / (rw - ra) * (rw / ra - 1.0);
     const int cx = lx + 1, cy = ly + 1, cz = lz + HR::ZH;
-    const double P0 = sP[R::idx(cx, cy, cz)];
+    const double P0 = (double)sP[R::idx(cx, cy, cz)];
     double sk = 0.0, su = 0.0;
 #pragma unroll
     for (int i = 1; i < G::Q; ++i) {
         const int k = R::idx(cx - G::c(i, 0), cy - G::c(i, 1), cz - G::c(i, 2));
-        sk += G::w(i) * ((WALL ? sP[k] + rho * sGD[k] : sP[k]) - P0);
+        sk += G::w(i) * ((WALL ? (double)sP[k] + rho * (double)sGD[k] : (double)sP[k]) - P0);
         double cu = 0.0;
 #pragma unroll
         for (int a = 0; a < DIMV; ++a) {
-            if (G::c(i, a) == 1) cu += sJ[a][k];
-            if (G::c(i, a) == -1) cu -= sJ[a][k];
+            if (G::c(i, a) == 1) cu += (double)sJ[a][k];
+            if (G::c(i, a) == -1) cu -= (double)sJ[a][k];
         }
         su += G::w(i) * cu;
     }
@@ -754,7 +753,7 @@ __global__ __launch_bounds__(256) void k_pressure(CaseTab cases, const int* hdr,
 {
     using Mo = Model<DIMV>;
     using R = typename Halo1<Mo, DIMV>::R;
-    __shared__ double sP[R::N], sGD[R::N], sJ[DIMV][R::N];
+    __shared__ AT sP[R::N], sGD[R::N], sJ[DIMV][R::N];
     const TileCtx t = tile_ctx<Mo>(cases, hdr, step_off);
     if (!t.active) return;
     CDesc& cs = *t.cs;
@@ -972,7 +971,20 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
 }
 
 template <int DIMV, class S>
-__global__ __launch_bounds__(256) void k_collide(CaseTab cases, const int* hdr, int step_off)
+// Occupancy target of the collision kernel in waves per SIMD (0 leaves the
+// register budget to the compiler).  Left alone the compiler takes ~175-195
+// VGPRs (2 waves); a budget of 168 (3 waves) costs a few dwords of spill and
+// hides enough more memory latency to run 10% (FP32) to 18% (FP16) faster;
+// 128 (4 waves) spills too much.
+#ifndef PULBM_COLLIDE_WAVES
+#define PULBM_COLLIDE_WAVES 3
+#endif
+#if PULBM_COLLIDE_WAVES > 0
+#define PULBM_COLLIDE_ATTR __attribute__((amdgpu_waves_per_eu(PULBM_COLLIDE_WAVES, PULBM_COLLIDE_WAVES)))
+#else
+#define PULBM_COLLIDE_ATTR
+#endif
+__global__ __launch_bounds__(256) PULBM_COLLIDE_ATTR void k_collide(CaseTab cases, const int* hdr, int step_off)
 {
     using Mo = Model<DIMV>;
     using H = typename Mo::H;

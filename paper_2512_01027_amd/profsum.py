@@ -25,12 +25,10 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ("csrc/kernels.hpp", "csrc/lattice.hpp", "csrc/codec.hpp", "csrc/pulbm.hip")
 
-# Itanium-mangled names rocprofv3 leaves for kernels templated on _Float16
-_DEMANGLE = {
-    "_ZN5pulbm9k_collideILi3EDF16_EEvPKPNS_7CaseDevEPKiiii": "pulbm::k_collide<3, _Float16>",
-    "_ZN5pulbm9k_momentsILi3EDF16_EEvPKPNS_7CaseDevEPKiiii": "pulbm::k_moments<3, _Float16>",
-    "_ZN5pulbm6k_initILi3EDF16_EEvPKPNS_7CaseDevEPKiiiPKdS8_S8_": "pulbm::k_init<3, _Float16>",
-}
+# rocprofv3 leaves kernels templated on _Float16 in their mangled form:
+# _ZN5pulbm<len><name>ILi<dim>E<type>E...
+_MANGLED = re.compile(r"_ZN5pulbm\d+(k_[a-z]+)ILi(\d)E(DF16_|[dft])E")
+_TYPES = {"DF16_": "_Float16", "d": "double", "f": "float", "t": "unsigned short"}
 
 
 def source_hash() -> str:
@@ -42,7 +40,9 @@ def source_hash() -> str:
 
 
 def short(name: str) -> str:
-    name = _DEMANGLE.get(name, name)
+    m = _MANGLED.match(name)
+    if m:
+        name = f"pulbm::{m.group(1)}<{m.group(2)}, {_TYPES[m.group(3)]}>"
     name = re.sub(r"\(.*", "", name)
     return name.replace("void ", "")
 
