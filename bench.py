@@ -133,12 +133,21 @@ def serving_leg(n_cases=64, step_scale=0.1):
     pois_b = SV.run_batched(reqs, budget)
     SV.set_arrivals(reqs, rate)
     pois_s = SV.run_sequential(reqs)
+    # the same request mix restricted to small cases (at most 64^3 / 256^2
+    # nodes), each far from filling the GPU on its own
+    small = SV.make_stream(n_cases, "fp16", step_scale, case_seed=4, max_nodes=64 ** 3)
+    SV.set_arrivals(small, None)
+    small_b = SV.run_batched(small, budget)
+    SV.set_arrivals(small, None)
+    small_s = SV.run_sequential(small)
     return {"saturated": SV.compare(burst_b, burst_s), "poisson": SV.compare(pois_b, pois_s),
+            "small_cases_saturated": SV.compare(small_b, small_s),
             "sample": (f"{n_cases} requests (seed 3): 75% 3D n in [32,192], 25% 2D n in [128,1024] "
                        f"(log-uniform), droplet / rising bubble, density ratio 10/100/1000, "
                        f"steps U{{1000..10000}} x {step_scale}; FP16 storage; batch budget "
                        f"{budget / 2**30:.0f} GiB; saturated: all at t=0; poisson: arrivals (seed 2) at "
-                       f"{rate:.2f}/s = 0.8 x batched capacity / mean work")}
+                       f"{rate:.2f}/s = 0.8 x batched capacity / mean work; small_cases: {n_cases} requests "
+                       f"(seed 4) of at most 64^3 nodes, all at t=0")}
 
 
 def cpu_baseline(cfg, fields):

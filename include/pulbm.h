@@ -124,12 +124,17 @@ void pulbm_destroy(pulbm_case* c);
 const char* pulbm_last_error(void);
 
 /* ------------------------------------------------------------------ serving
- * A batch keeps many cases resident in one device memory budget and advances
- * all active cases together: each launch covers the tiles of every resident
- * case of a lattice (2D or 3D), and a k-step advance is one replay of a
- * captured HIP graph.  Each case runs exactly its requested number of steps;
- * its arithmetic is the same as a single case's, so results do not depend on
- * which other cases share the batch.  A batch uses one storage precision. */
+ * A batch keeps many cases resident in one device arena (the budget,
+ * allocated once at creation) and advances all active cases together: each
+ * launch covers the tiles of every resident case of a lattice (2D or 3D), and
+ * a k-step advance is one replay of a captured HIP graph on the batch stream.
+ * Each case runs exactly its requested number of steps; its arithmetic is the
+ * same as a single case's, so results do not depend on which other cases
+ * share the batch.  A batch uses one storage precision.
+ *
+ * Admissions and read-backs run on a second stream of the batch, so they
+ * overlap the advances already queued.  The calls of one batch must come
+ * from one thread at a time. */
 typedef struct pulbm_batch pulbm_batch;
 
 int pulbm_batch_create(size_t hbm_budget, int32_t store, int32_t max_slots, void* hip_stream,
@@ -141,9 +146,14 @@ int pulbm_batch_admit(pulbm_batch* b, const pulbm_params* p, const double* phi, 
                       const double* u, int64_t nsteps, int32_t* slot);
 /* Queue ksteps steps of every active case (a captured graph per ksteps). */
 int pulbm_batch_advance(pulbm_batch* b, int32_t ksteps);
-/* Slots whose cases have finished (synchronises); fills up to cap ids. */
+/* Slots whose cases have finished; fills up to cap ids, *ndone = how many.
+ * Waits for every queued advance but the newest one (for all of them when no
+ * resident case has steps left), so that the newest keeps the GPU busy while
+ * the caller takes and admits cases. */
 int pulbm_batch_poll(pulbm_batch* b, int32_t* done_slots, int32_t cap, int32_t* ndone);
-/* Read a finished case's phi, P, u (as pulbm_read_fields) and free its slot. */
+/* Read a case's phi, P, u (as pulbm_read_fields; for a case that has not
+ * finished: its state after every queued advance) and free its slot.  Its
+ * memory returns to the budget once the advances queued so far complete. */
 int pulbm_batch_take(pulbm_batch* b, int32_t slot, double* phi, double* P, double* u);
 /* Bytes of the budget in use, number of active cases. */
 int pulbm_batch_usage(const pulbm_batch* b, size_t* used, int32_t* active);

@@ -129,8 +129,10 @@ __device__ __forceinline__ TileCtx tile_ctx(CaseTab cases, const int* hdr_, int 
     const PULBM_CST uint64_t* tab = (const PULBM_CST uint64_t*)(const void*)cases;
     t.cs = (CDesc*)(uintptr_t)tab[ci];
     CDesc& cs = *t.cs;
-    t.step = cs.step + step_off;
-    t.active = t.step < cs.step_end;
+    // step_off < 0: read mode (the moment stage of the current state, run
+    // whatever the case's step limit)
+    t.step = cs.step + (step_off > 0 ? step_off : 0);
+    t.active = step_off < 0 || t.step < cs.step_end;
     int lt = tile - tstart[ci];
     const int tx = lt % cs.ntx;
     lt /= cs.ntx;
@@ -1128,14 +1130,16 @@ __global__ __launch_bounds__(256) void k_diag(const CaseDev* __restrict__ csp, d
     }
 }
 
+// one wave per value: lane l takes blocks l, l + 64, ... in order, then a
+// fixed shuffle tree (the result does not depend on scheduling)
 __global__ __launch_bounds__(64) void k_diag_final(const double* __restrict__ partial, int nblocks,
                                                    double* __restrict__ out)
 {
-    const int k = threadIdx.x;
-    if (k >= kDiagVals) return;
+    const int k = blockIdx.x, lane = threadIdx.x;
     double r = 0.0;
-    for (int b = 0; b < nblocks; ++b) r = k == 7 ? fmax(r, partial[b * kDiagVals + k]) : r + partial[b * kDiagVals + k];
-    out[k] = r;
+    for (int b = lane; b < nblocks; b += 64) r = k == 7 ? fmax(r, partial[b * kDiagVals + k]) : r + partial[b * kDiagVals + k];
+    r = k == 7 ? wave_max(r) : wave_sum(r);
+    if (lane == 0) out[k] = r;
 }
 
 }  // namespace pulbm

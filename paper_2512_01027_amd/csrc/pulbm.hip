@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <string>
 #include <vector>
@@ -225,10 +226,14 @@ int upload_desc(pulbm_case* c)
     return PULBM_OK;
 }
 
+// The moment stage on the current state without changing it.  Launched in
+// read mode (step offset -1): it runs whatever the case's step limit, so a
+// case that has finished its steps in a serving batch can be read while its
+// descriptor stays untouched.
 int read_pass(pulbm_case* c)
 {
     for (int w = 0; w < kReadKernels; ++w)
-        launch(c->p.dim, c->p.store, c->stream, c->tab, c->hdr, grid_of(c->ntiles), 0, w);
+        launch(c->p.dim, c->p.store, c->stream, c->tab, c->hdr, grid_of(c->ntiles), -1, w);
     HIPC(hipGetLastError());
     return PULBM_OK;
 }
@@ -464,7 +469,7 @@ extern "C" int pulbm_diagnostics(pulbm_case* c, pulbm_diag* d)
         hipLaunchKernelGGL(k_diag<double>, dim3(kDiagBlocks), dim3(256), 0, c->stream, c->d, partial);
     else
         hipLaunchKernelGGL(k_diag<float>, dim3(kDiagBlocks), dim3(256), 0, c->stream, c->d, partial);
-    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, c->stream, partial, kDiagBlocks, dd);
+    hipLaunchKernelGGL(k_diag_final, dim3(kDiagVals), dim3(64), 0, c->stream, partial, kDiagBlocks, dd);
     HIPC(hipGetLastError());
     double r[kDiagVals];
     HIPC(hipMemcpyAsync(r, dd, sizeof r, hipMemcpyDeviceToHost, c->stream));
@@ -579,22 +584,40 @@ extern "C" int64_t pulbm_steps_done(const pulbm_case* c) { return c ? c->step : 
 struct pulbm_batch {
     size_t budget = 0, used = 0;
     int store = 0, max_slots = 0;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;  // advances
+    hipStream_t side = nullptr;    // admissions and read-backs
     bool own_stream = false;
     // one device arena of the whole budget; cases are carved from it
     // (first fit, 256-byte granules, neighbouring holes merged on release)
     char* arena = nullptr;
     std::map<size_t, size_t> holes;  // offset -> bytes
+    struct Release {
+        int64_t after;  // advances up to this one may still read the block
+        size_t off, bytes;
+    };
+    std::vector<Release> retiring;
+    // graphs replaced while advances that replay them may still be queued
+    std::vector<std::pair<int64_t, hipGraphExec_t>> old_graphs;
     struct Slot {
         pulbm_case* c = nullptr;
         int64_t end = 0;
+        int64_t finish = -1;  // advance that takes the case to its end
         size_t bytes = 0, off = 0;
     };
     std::vector<Slot> slots;
-    // per lattice dimension: device table of case pointers + its header
+    // advances in flight: sequence number -> completion event
+    int64_t enqueued = 0, completed = 0;
+    std::deque<std::pair<int64_t, hipEvent_t>> inflight;
+    std::vector<hipEvent_t> spare_events;
+    // per lattice dimension: device table of case pointers + its header,
+    // filled by stream-ordered copies from pinned host staging (two buffers,
+    // each reused once its previous copy has executed)
     struct Tab {
         CaseDev** dtab = nullptr;
         int* dhdr = nullptr;  // {ncases, tiles, tstart[0..ncases]}
+        char* stage[2] = {nullptr, nullptr};
+        hipEvent_t staged[2] = {nullptr, nullptr};
+        int which = 0;
         int cap = 0, ncases = 0, tiles = 0, grid = 0;
         std::map<int, hipGraphExec_t> graphs;  // by ksteps, captured for `grid` blocks
     } tab[2];
@@ -633,52 +656,97 @@ void arena_give(pulbm_batch* b, size_t off, size_t bytes)
     }
 }
 
-void drop_graphs(pulbm_batch::Tab& t)
+// Retire completed advances (wait_upto: block until that one is done too)
+// and release the arena blocks no advance can read any more.
+int sync_advances(pulbm_batch* b, int64_t wait_upto)
 {
-    for (auto& kv : t.graphs) (void)hipGraphExecDestroy(kv.second);
+    while (!b->inflight.empty()) {
+        auto& f = b->inflight.front();
+        if (f.first <= wait_upto) {
+            HIPC(hipEventSynchronize(f.second));
+        } else {
+            const hipError_t q = hipEventQuery(f.second);
+            if (q == hipErrorNotReady) break;
+            if (q != hipSuccess) return fail(PULBM_EDEVICE, "advance failed: %s", hipGetErrorString(q));
+        }
+        b->completed = f.first;
+        b->spare_events.push_back(f.second);
+        b->inflight.pop_front();
+    }
+    if (b->inflight.empty()) b->completed = b->enqueued;
+    for (size_t i = 0; i < b->old_graphs.size();) {
+        if (b->old_graphs[i].first <= b->completed) {
+            (void)hipGraphExecDestroy(b->old_graphs[i].second);
+            b->old_graphs[i] = b->old_graphs.back();
+            b->old_graphs.pop_back();
+        } else {
+            ++i;
+        }
+    }
+    for (size_t i = 0; i < b->retiring.size();) {
+        if (b->retiring[i].after <= b->completed) {
+            arena_give(b, b->retiring[i].off, b->retiring[i].bytes);
+            b->used -= b->retiring[i].bytes;
+            b->retiring[i] = b->retiring.back();
+            b->retiring.pop_back();
+        } else {
+            ++i;
+        }
+    }
+    return PULBM_OK;
+}
+
+// Graphs of the old grid are destroyed once the advances queued so far, which
+// may replay them, have completed.
+void drop_graphs(pulbm_batch* b, pulbm_batch::Tab& t)
+{
+    for (auto& kv : t.graphs) b->old_graphs.emplace_back(b->enqueued, kv.second);
     t.graphs.clear();
 }
 
 int rebuild_tables(pulbm_batch* b)
 {
-    HIPC(hipStreamSynchronize(b->stream));
     for (int di = 0; di < 2; ++di) {
         const int dim = di + 2;
         pulbm_batch::Tab& t = b->tab[di];
-        std::vector<CaseDev*> ptr;
-        std::vector<int> hdr{0, 0, 0};
-        for (auto& s : b->slots)
-            if (s.c && s.c->p.dim == dim) {
-                ptr.push_back(s.c->d);
-                hdr.push_back(hdr.back() + s.c->ntiles);
-            }
-        t.ncases = (int)ptr.size();
-        t.tiles = hdr.back();
-        hdr[0] = t.ncases;
-        hdr[1] = t.tiles;
-        if (t.ncases == 0) continue;
-        if (t.cap < t.ncases) {
-            drop_graphs(t);
-            if (t.dtab) (void)hipFree(t.dtab);
-            if (t.dhdr) (void)hipFree(t.dhdr);
-            t.dtab = nullptr;
-            t.dhdr = nullptr;
-            t.cap = std::max(t.ncases, b->max_slots);
+        if (t.cap == 0) {  // sized once for every slot
+            t.cap = b->max_slots;
             HIPC(hipMalloc((void**)&t.dtab, t.cap * sizeof(CaseDev*)));
             HIPC(hipMalloc((void**)&t.dhdr, (t.cap + 3) * sizeof(int)));
+            for (int k = 0; k < 2; ++k) {
+                HIPC(hipHostMalloc((void**)&t.stage[k], t.cap * sizeof(CaseDev*) + (t.cap + 3) * sizeof(int),
+                                   hipHostMallocDefault));
+                HIPC(hipEventCreateWithFlags(&t.staged[k], hipEventDisableTiming));
+            }
         }
+        t.which ^= 1;
+        HIPC(hipEventSynchronize(t.staged[t.which]));  // its last copy has executed
+        CaseDev** ptr = (CaseDev**)t.stage[t.which];
+        int* hdr = (int*)(t.stage[t.which] + t.cap * sizeof(CaseDev*));
+        int n = 0;
+        hdr[2] = 0;
+        for (auto& s : b->slots)
+            if (s.c && s.c->p.dim == dim) {
+                ptr[n] = s.c->d;
+                hdr[3 + n] = hdr[2 + n] + s.c->ntiles;
+                ++n;
+            }
+        t.ncases = n;
+        t.tiles = hdr[2 + n];
+        hdr[0] = n;
+        hdr[1] = t.tiles;
         // every block of a launch that finds no tile still costs a dispatch,
         // so the captured grid follows the tile count: recapture when it no
         // longer covers the tiles or exceeds them by more than a quarter
         const int g = grid_of(t.tiles);
-        if (g > t.grid || 4 * t.grid > 5 * g) {
-            drop_graphs(t);
+        if (n && (g > t.grid || 4 * t.grid > 5 * g)) {
+            drop_graphs(b, t);
             t.grid = g;
         }
-        HIPC(hipMemcpyAsync(t.dtab, ptr.data(), t.ncases * sizeof(CaseDev*), hipMemcpyHostToDevice, b->stream));
-        HIPC(hipMemcpyAsync(t.dhdr, hdr.data(), hdr.size() * sizeof(int), hipMemcpyHostToDevice, b->stream));
+        if (n) HIPC(hipMemcpyAsync(t.dtab, ptr, n * sizeof(CaseDev*), hipMemcpyHostToDevice, b->stream));
+        HIPC(hipMemcpyAsync(t.dhdr, hdr, (3 + n) * sizeof(int), hipMemcpyHostToDevice, b->stream));
+        HIPC(hipEventRecord(t.staged[t.which], b->stream));
     }
-    HIPC(hipStreamSynchronize(b->stream));
     b->dirty = false;
     return PULBM_OK;
 }
@@ -697,25 +765,27 @@ extern "C" int pulbm_batch_create(size_t budget, int32_t store, int32_t max_slot
     b->budget = budget;
     b->store = store;
     b->max_slots = max_slots;
+    b->slots.resize(max_slots);
+    hipError_t e = hipSuccess;
     if (budget) {
-        hipError_t e = hipMalloc((void**)&b->arena, budget);
+        e = hipMalloc((void**)&b->arena, budget);
         if (e != hipSuccess) {
-            delete b;
+            b->arena = nullptr;
+            pulbm_batch_destroy(b);
             return fail(PULBM_ENOMEM, "batch arena of %zu bytes: %s", budget, hipGetErrorString(e));
         }
         b->holes[0] = budget;
     }
     b->stream = (hipStream_t)hip_stream;
     if (!b->stream) {  // graph capture needs a stream other than the null stream
-        hipError_t e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
-        if (e != hipSuccess) {
-            if (b->arena) (void)hipFree(b->arena);
-            delete b;
-            return fail(PULBM_EDEVICE, "hipStreamCreate failed: %s", hipGetErrorString(e));
-        }
-        b->own_stream = true;
+        e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+        b->own_stream = e == hipSuccess;
     }
-    b->slots.resize(max_slots);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        pulbm_batch_destroy(b);
+        return fail(PULBM_EDEVICE, "hipStreamCreate failed: %s", hipGetErrorString(e));
+    }
     *out = b;
     return PULBM_OK;
 }
@@ -728,6 +798,7 @@ extern "C" int pulbm_batch_admit(pulbm_batch* b, const pulbm_params* p, const do
     if (rc) return rc;
     if (p->store != b->store) return fail(PULBM_EINVAL, "case store %d differs from the batch's %d", p->store, b->store);
     if (nsteps < 0) return fail(PULBM_EINVAL, "nsteps < 0");
+    if ((rc = sync_advances(b, 0))) return rc;  // picks up released blocks
     const size_t bytes = align_up(make_layout(*p).total);
     int free_slot = -1;
     for (int i = 0; i < b->max_slots; ++i)
@@ -736,25 +807,29 @@ extern "C" int pulbm_batch_admit(pulbm_batch* b, const pulbm_params* p, const do
     size_t off = 0;
     if (b->used + bytes > b->budget || !arena_take(b, bytes, &off))
         return fail(PULBM_EAGAIN, "needs %zu bytes, %zu of %zu free", bytes, b->budget - b->used, b->budget);
+    // the case works on the side stream: its set-up overlaps the advances
     pulbm_case* c = nullptr;
-    if ((rc = pulbm_create(p, b->arena + off, bytes, b->stream, &c))) {
+    if ((rc = pulbm_create(p, b->arena + off, bytes, b->side, &c))) {
         arena_give(b, off, bytes);
         return rc;
     }
-    if (!rc) rc = pulbm_init_fields(c, phi, P, u);
+    rc = pulbm_init_fields(c, phi, P, u);
     if (!rc) {
         c->h.step_end = nsteps;
         rc = upload_desc(c);
     }
+    if (!rc && hipStreamSynchronize(b->side) != hipSuccess) rc = fail(PULBM_EDEVICE, "case set-up failed");
     if (rc) {
         pulbm_destroy(c);
         arena_give(b, off, bytes);
         return rc;
     }
-    b->slots[free_slot].c = c;
-    b->slots[free_slot].end = nsteps;
-    b->slots[free_slot].bytes = bytes;
-    b->slots[free_slot].off = off;
+    pulbm_batch::Slot& s = b->slots[free_slot];
+    s.c = c;
+    s.end = nsteps;
+    s.finish = nsteps == 0 ? 0 : -1;
+    s.bytes = bytes;
+    s.off = off;
     b->used += bytes;
     b->dirty = true;
     *slot = free_slot;
@@ -765,10 +840,9 @@ extern "C" int pulbm_batch_advance(pulbm_batch* b, int32_t ksteps)
 {
     if (!b) return fail(PULBM_EINVAL, "batch is NULL");
     if (ksteps < 1 || ksteps > 4096) return fail(PULBM_EINVAL, "ksteps must be in [1, 4096]");
-    if (b->dirty) {
-        int rc = rebuild_tables(b);
-        if (rc) return rc;
-    }
+    int rc = sync_advances(b, 0);
+    if (rc) return rc;
+    if (b->dirty && (rc = rebuild_tables(b))) return rc;
     for (int di = 0; di < 2; ++di) {
         pulbm_batch::Tab& t = b->tab[di];
         if (t.ncases == 0) continue;
@@ -788,11 +862,23 @@ extern "C" int pulbm_batch_advance(pulbm_batch* b, int32_t ksteps)
         }
         HIPC(hipGraphLaunch(it->second, b->stream));
     }
+    hipEvent_t ev = nullptr;
+    if (!b->spare_events.empty()) {
+        ev = b->spare_events.back();
+        b->spare_events.pop_back();
+    } else {
+        HIPC(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    }
+    HIPC(hipEventRecord(ev, b->stream));
+    const int64_t seq = ++b->enqueued;
+    b->inflight.emplace_back(seq, ev);
     // host bookkeeping of every resident case
     for (auto& s : b->slots)
         if (s.c) {
+            const int64_t was = s.c->step;
             s.c->step = std::min<int64_t>(s.c->step + ksteps, s.end);
             s.c->h.step = s.c->step;
+            if (was < s.end && s.c->step >= s.end) s.finish = seq;
         }
     return PULBM_OK;
 }
@@ -800,13 +886,21 @@ extern "C" int pulbm_batch_advance(pulbm_batch* b, int32_t ksteps)
 extern "C" int pulbm_batch_poll(pulbm_batch* b, int32_t* done, int32_t cap, int32_t* ndone)
 {
     if (!b || !ndone) return fail(PULBM_EINVAL, "NULL argument");
-    HIPC(hipStreamSynchronize(b->stream));
+    // keep the newest advance queued while other cases still have steps to
+    // run; wait for the ones before it
+    bool pending = false;
+    for (auto& s : b->slots)
+        if (s.c && s.c->step < s.end) pending = true;
+    int rc = sync_advances(b, pending ? b->enqueued - 1 : b->enqueued);
+    if (rc) return rc;
     int k = 0;
-    for (int i = 0; i < b->max_slots; ++i)
-        if (b->slots[i].c && b->slots[i].c->step >= b->slots[i].end) {
+    for (int i = 0; i < b->max_slots; ++i) {
+        const pulbm_batch::Slot& s = b->slots[i];
+        if (s.c && s.finish >= 0 && s.finish <= b->completed) {
             if (done && k < cap) done[k] = i;
             ++k;
         }
+    }
     *ndone = k;
     return PULBM_OK;
 }
@@ -815,19 +909,22 @@ extern "C" int pulbm_batch_take(pulbm_batch* b, int32_t slot, double* phi, doubl
 {
     if (!b || slot < 0 || slot >= b->max_slots || !b->slots[slot].c) return fail(PULBM_EINVAL, "bad slot");
     pulbm_batch::Slot& s = b->slots[slot];
-    HIPC(hipStreamSynchronize(b->stream));
-    // leaving the batch: lift the step limit so the read pass runs at any step
-    s.c->h.step_end = INT64_MAX;
-    int rc = upload_desc(s.c);
-    if (rc) return rc;
+    int rc = PULBM_OK;
+    if (s.finish < 0) {  // not finished: wait for everything queued
+        if ((rc = sync_advances(b, b->enqueued))) return rc;
+    } else if ((rc = sync_advances(b, s.finish))) {
+        return rc;
+    }
+    // read on the side stream while later advances run (the case is idle in
+    // them: its descriptor caps its steps)
     rc = pulbm_read_fields(s.c, phi, P, u);
     if (rc) return rc;
     pulbm_destroy(s.c);
-    arena_give(b, s.off, s.bytes);
-    b->used -= s.bytes;
+    // advances already queued may still read the case's descriptor
+    b->retiring.push_back({b->enqueued, s.off, s.bytes});
     s = pulbm_batch::Slot();
     b->dirty = true;
-    return PULBM_OK;
+    return sync_advances(b, 0);
 }
 
 extern "C" int pulbm_batch_usage(const pulbm_batch* b, size_t* used, int32_t* active)
@@ -845,15 +942,24 @@ extern "C" int pulbm_batch_usage(const pulbm_batch* b, size_t* used, int32_t* ac
 extern "C" void pulbm_batch_destroy(pulbm_batch* b)
 {
     if (!b) return;
-    (void)hipStreamSynchronize(b->stream);
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    if (b->side) (void)hipStreamSynchronize(b->side);
     for (auto& s : b->slots)
         if (s.c) pulbm_destroy(s.c);
     for (auto& t : b->tab) {
-        drop_graphs(t);
+        for (auto& kv : t.graphs) (void)hipGraphExecDestroy(kv.second);
         if (t.dtab) (void)hipFree(t.dtab);
         if (t.dhdr) (void)hipFree(t.dhdr);
+        for (int k = 0; k < 2; ++k) {
+            if (t.stage[k]) (void)hipHostFree(t.stage[k]);
+            if (t.staged[k]) (void)hipEventDestroy(t.staged[k]);
+        }
     }
+    for (auto& g : b->old_graphs) (void)hipGraphExecDestroy(g.second);
+    for (auto& f : b->inflight) (void)hipEventDestroy(f.second);
+    for (auto ev : b->spare_events) (void)hipEventDestroy(ev);
     if (b->arena) (void)hipFree(b->arena);
+    if (b->side) (void)hipStreamDestroy(b->side);
     if (b->own_stream) (void)hipStreamDestroy(b->stream);
     delete b;
 }

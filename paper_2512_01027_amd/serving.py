@@ -46,10 +46,11 @@ def make_stream(n_cases: int, store: str = "fp16", step_scale: float = 0.1, case
     rng = np.random.Generator(np.random.PCG64(case_seed))
     out = []
     while len(out) < n_cases:
-        cfg, f, steps, kind = W.serving_case(rng, store)
-        nodes = cfg["nx"] * cfg["ny"] * cfg["nz"]
-        if max_nodes is not None and nodes > max_nodes:
+        case = W.serving_case(rng, store, max_nodes)
+        if case is None:
             continue
+        cfg, f, steps, kind = case
+        nodes = cfg["nx"] * cfg["ny"] * cfg["nz"]
         out.append(Request(len(out), cfg, f, max(1, int(round(steps * step_scale))), kind, 0.0, nodes))
     return out
 
@@ -76,8 +77,15 @@ def _summary(reqs, makespan):
             "latency_mean_s": round(float(lat.mean()), 4)}
 
 
-def run_batched(reqs, hbm_budget: int, store: str = "fp16", k: int = 50, max_slots: int = 64):
-    """Continuous batching.  Returns the summary; sets each request's done."""
+def run_batched(reqs, hbm_budget: int, store: str = "fp16", k: int = 50, max_slots: int = 64,
+                fill_nodes: int = 12 << 20, admit_per_round: int = 4):
+    """Continuous batching.  Returns the summary; sets each request's done.
+
+    Requests are admitted in arrival order, a few per round so that the GPU
+    starts on the first ones while later ones are set up, and only while the
+    resident cases hold fewer than fill_nodes nodes (enough to fill the GPU:
+    more would only share it among more cases and lengthen every latency).
+    """
     bt = B.Batch(hbm_budget, store=store, max_slots=max_slots)
     pending = sorted(reqs, key=lambda r: r.arrival)
     waiting: list[Request] = []
@@ -91,13 +99,18 @@ def run_batched(reqs, hbm_budget: int, store: str = "fp16", k: int = 50, max_slo
         while i < len(pending) and pending[i].arrival <= now:
             waiting.append(pending[i])
             i += 1
-        while waiting:
+        admitted = 0
+        while waiting and admitted < admit_per_round:
+            held = sum(r.nodes for r in resident.values())
+            if resident and held + waiting[0].nodes > fill_nodes:
+                break
             r = waiting[0]
             slot = bt.admit(r.cfg, *r.fields, r.steps)
             if slot is None:
                 break
             resident[slot] = r
             waiting.pop(0)
+            admitted += 1
         peak = max(peak, len(resident))
         if not resident:
             if i < len(pending):
@@ -112,8 +125,7 @@ def run_batched(reqs, hbm_budget: int, store: str = "fp16", k: int = 50, max_slo
     makespan = max(r.done for r in reqs) - min(r.arrival for r in reqs)
     bt.close()
     out = _summary(reqs, makespan)
-    out["peak_resident"] = peak
-    out["advance_steps"] = k
+    out.update({"peak_resident": peak, "advance_steps": k, "fill_nodes": fill_nodes})
     return out
 
 

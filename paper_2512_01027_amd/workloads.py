@@ -163,10 +163,11 @@ def config_dam_break_3d(nx=512, ny=256, nz=256, store="fp16"):
     return cfg, (phi, P, u), 20000
 
 
-def serving_case(rng, store="fp16"):
+def serving_case(rng, store="fp16", max_nodes=None):
     """One request of the serving stream: 75% 3D (n log-uniform in [32, 192]),
     25% 2D (n log-uniform in [128, 1024]); static droplet or rising bubble;
-    density ratio in {10, 100, 1000}; R = n/6; 1000..10000 steps."""
+    density ratio in {10, 100, 1000}; R = n/6; 1000..10000 steps.  With
+    max_nodes, a request of more nodes is drawn but not built (None)."""
     is3d = rng.uniform() < 0.75
     if is3d:
         n = int(round(math.exp(rng.uniform(math.log(32), math.log(192)))))
@@ -176,6 +177,8 @@ def serving_case(rng, store="fp16"):
     ratio = float(rng.choice([10.0, 100.0, 1000.0]))
     steps = int(rng.integers(1000, 10001))
     dim = 3 if is3d else 2
+    if max_nodes is not None and n ** dim > max_nodes:
+        return None
     R = n / 6.0
     if kind == "droplet":
         cfg = base_case(dim, n, n, n, rho_heavy=ratio, rho_light=1.0, sigma=0.005 if is3d else 0.01,
