@@ -13,11 +13,15 @@
  *
  * Readings of points the paper leaves open (each is also listed in the design doc):
  *  R1  one LKS pass with no iteration, in the order the paper writes the two
- *      formulas: P first, from K_i of the previous step's P and, in the
- *      omega term, the velocity the streamed populations carry,
- *      u* = sum_i g_i c_i, at x - c_i; then u = sum_i (g_i + K_i) c_i with K_i
- *      of the new P.  rho in K_i is the current rho(x).  Other orders couple
- *      pressure and velocity by forward Euler (unstable at small viscosity).
+ *      formulas.  The pressure equation holds P on both sides (through K_i);
+ *      its one evaluation starts from the pressure the streamed populations
+ *      carry, P* = rho_ref T sum_i g_i: P from K_i of P* and, in the omega
+ *      term, the velocity the populations carry, u* = sum_i g_i c_i, at
+ *      x - c_i; then u = sum_i (g_i + K_i) c_i with K_i of the new P.  rho in
+ *      K_i is the current rho(x).  Starting from the previous step's P instead
+ *      couples pressure and velocity by forward Euler and is unstable in the
+ *      light fluid below nu ~ 5e-3; from P* the scheme stays stable to
+ *      nu ~ 1e-3.
  *  R2  rho, tau and omega use phi clamped to [0,1]; theta, mu, h^eq use raw phi.
  *  R3  the velocity moment sums g_i + K_i (the paper's f_i is read as g_i).
  *  R4  nu in B and sigma_lm is the local T(tau_mix - 1/2).
@@ -72,8 +76,10 @@ struct pulbm_oracle_case {
     size_t N;
     double *h, *g;       /* post-streaming distributions [q][N] */
     double *hn, *gn;     /* streaming targets */
-    double *Plag;        /* P of the previous moment stage */
+    double *Plag;        /* P of the previous moment stage (restart image; the step
+                            reads the pressure the populations carry instead) */
     double *J;           /* velocity moment of the populations (work array) */
+    double *Ps;          /* pressure the populations carry, rho_ref T sum g (work) */
     double *phi, *rho, *P, *u;
     int64_t step;
 };
@@ -235,12 +241,12 @@ static double ustar_at(const pulbm_oracle_case* C, const double* J, int a, const
     return v;
 }
 
-/* phi = sum h; P and u from Sec. II "The pressure and velocity are calculated
- * as follows", one LKS pass without iteration (reading R1), in the order the
- * paper writes the two formulas: P first, with K_i of the previous step's
- * pressure and, in the omega term, the velocity the streamed populations
- * carry, u* = sum g c, at x - c_i; then u = sum (g_i + K_i) c_i with K_i of
- * the new pressure. */
+/* phi = sum h; P and u from the pressure and velocity formulas of Sec. II,
+ * one LKS pass without iteration (reading R1), in the order the paper writes
+ * them: P first, with K_i of the pressure the populations carry,
+ * P* = rho_ref T sum g, and, in the omega term, the velocity they carry,
+ * u* = sum g c, at x - c_i; then u = sum (g_i + K_i) c_i with K_i of the new
+ * pressure. */
 static void moments(const pulbm_oracle_case* C, double* phi, double* rho, double* P, double* u)
 {
     const model* M = &C->m;
@@ -250,7 +256,8 @@ static void moments(const pulbm_oracle_case* C, double* phi, double* rho, double
     const double ra = M->p.rho_light, rw = M->p.rho_heavy;
     const size_t N = C->N;
     double* J = C->J;
-    /* pass 1: phi, rho, u* */
+    double* Ps = C->Ps;
+    /* pass 1: phi, rho, u*, P* */
 #pragma omp parallel for schedule(static)
     for (size_t n = 0; n < N; ++n) {
         double ph = 0.0;
@@ -264,6 +271,9 @@ static void moments(const pulbm_oracle_case* C, double* phi, double* rho, double
             for (int i = 0; i < G->q; ++i) s += C->g[(size_t)i * N + n] * G->c[i][a];
             J[(size_t)a * N + n] = s;
         }
+        double sg = 0.0;
+        for (int i = 0; i < G->q; ++i) sg += C->g[(size_t)i * N + n];
+        Ps[n] = ra * T * sg;
     }
     /* pass 2: P */
 #pragma omp parallel for collapse(2) schedule(static)
@@ -277,7 +287,7 @@ static void moments(const pulbm_oracle_case* C, double* phi, double* rho, double
                 double s1 = 0.0, s2 = 0.0;
                 for (int i = 0; i < G->q; ++i) {
                     int d[3] = {-G->c[i][0], -G->c[i][1], -G->c[i][2]};
-                    double K = k_term(C, C->Plag, x, i, r);
+                    double K = k_term(C, Ps, x, i, r);
                     s1 += C->g[(size_t)i * N + n] + (1.0 + omega) * K;
                     double cu = 0.0;
                     for (int a = 0; a < dim; ++a) cu += G->c[i][a] * ustar_at(C, J, a, x, d);
@@ -513,11 +523,12 @@ int pulbm_oracle_create(const pulbm_oracle_params* p, pulbm_oracle_case** out)
     C->gn = (double*)calloc((size_t)qg * N, sizeof(double));
     C->Plag = (double*)calloc(N, sizeof(double));
     C->J = (double*)calloc(3 * N, sizeof(double));
+    C->Ps = (double*)calloc(N, sizeof(double));
     C->phi = (double*)calloc(N, sizeof(double));
     C->rho = (double*)calloc(N, sizeof(double));
     C->P = (double*)calloc(N, sizeof(double));
     C->u = (double*)calloc(3 * N, sizeof(double));
-    if (!C->h || !C->hn || !C->g || !C->gn || !C->Plag || !C->J || !C->phi || !C->rho ||
+    if (!C->h || !C->hn || !C->g || !C->gn || !C->Plag || !C->J || !C->Ps || !C->phi || !C->rho ||
         !C->P || !C->u) {
         pulbm_oracle_destroy(C);
         return -2;
@@ -535,6 +546,7 @@ void pulbm_oracle_destroy(pulbm_oracle_case* C)
     free(C->gn);
     free(C->Plag);
     free(C->J);
+    free(C->Ps);
     free(C->phi);
     free(C->rho);
     free(C->P);

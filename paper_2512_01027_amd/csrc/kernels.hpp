@@ -3,11 +3,11 @@
 //
 // One time step is four launches over every resident case:
 //   k_moments  per node, no halo: gathers h and g (AA pattern) and writes
-//              phi = sum h, u* = sum g c, S = rho_ref T sum g (without the
-//              pressure carried by the rest population) and M2 = sum g c c.
+//              phi = sum h, u* = sum g c, P* = rho_ref T sum g (the pressure
+//              the populations carry; the stored rest population lacks the
+//              previous P, which is added back) and M2 = sum g c c.
 //   k_pressure 1-halo LDS tile, FP64 arithmetic: the pressure formula of
-//              Sec. II with K_i of the previous-step pressure and, in the
-//              omega term, u* at x - c_i.
+//              Sec. II with K_i of P* and, in the omega term, u* at x - c_i.
 //   k_velocity 1-halo LDS tile: u = sum_i (g_i + K_i) c_i with K_i of the new
 //              pressure, i.e. u = u* - D P / rho.
 //   k_collide  1-halo LDS tile of phi and u: the isotropic central
@@ -57,7 +57,9 @@ struct CaseDev {
     void* phi[2];      // N each: phi of this step's moments at phi[step & 1]; phi[(step + 1) & 1]
                        // keeps the previous step's, the reference of the 2-byte h codec
     void* J;           // dim*N  scratch: u* = sum g c
-    void* S;           // N      scratch: rho_ref T (sum g without the pressure part)
+    void* Ps;          // N      scratch: P* = previous P + rho_ref T sum g, the pressure the
+                       //        streamed populations carry (the rest population holds
+                       //        g_0 - P/(rho_ref T), so the previous P is added back)
     void* M2;          // 3 (2D) or 6 (3D) * N scratch: sum g c c
     void* U;           // dim*N  velocity u of the current step
     double rho_a, rho_w, tau_a, tau_w, tau_phi, M, W, sigma, lambda_b;
@@ -615,7 +617,7 @@ __device__ __forceinline__ CT h_reference(void* phi_prev, uint32_t n)
     else return (CT)0;
 }
 
-// --- moments: phi, u* = sum g c, S, M2 (per node; no halo)
+// --- moments: phi, u* = sum g c, P*, M2 (per node; no halo)
 template <int DIMV, class S, bool WALL>
 __device__ __forceinline__ void moments_node(CDesc& cs, int x, int y, int z, bool odd)
 {
@@ -666,7 +668,9 @@ __device__ __forceinline__ void moments_node(CDesc& cs, int x, int y, int z, boo
     const Slots<CT> Js = slots<CT>(cs.J, cs.N), Ms = slots<CT>(cs.M2, cs.N);
 #pragma unroll
     for (int a = 0; a < DIMV; ++a) *Js.at(a, na) = J[a];
-    *at_node<CT>(cs.S, n) = (CT)(cs.rho_a * kT) * sum;
+    using AT = CT;
+    const double Pprev = (double)*at_node<AT>(cs.P[odd ? 1 : 0], n);
+    *at_node<AT>(cs.Ps, n) = (AT)(Pprev + cs.rho_a * kT * (double)sum);
     constexpr int NM = DIMV == 2 ? 3 : 6;
 #pragma unroll
     for (int k = 0; k < NM; ++k) *Ms.at(k, na) = m2[k];
@@ -689,16 +693,17 @@ __global__ __launch_bounds__(256) void k_moments(CaseTab cases, const int* hdr, 
 }
 
 // --- pressure (Sec. II): P = rho_ref T sum_i (g_i + (1 + omega) K_i)
-//     + omega rho_ref sum_i w_i c_i . u*(x - c_i), K_i from the previous
-//     pressure.  FP64 arithmetic whatever the storage precision; the tile is
-//     staged in LDS in the storage type (exact) and widened at use.
+//     + omega rho_ref sum_i w_i c_i . u*(x - c_i), one evaluation of this
+//     equation (which holds P on both sides, through K_i) started from the
+//     pressure the streamed populations carry, P* = rho_ref T sum g: K_i from
+//     P*.  FP64 arithmetic whatever the storage precision; the tile is staged
+//     in LDS in the storage type (exact) and widened at use.
 template <int DIMV, class AT, bool WALL, class R>
 __device__ __forceinline__ void pressure_tile(CDesc& cs, const TileCtx& t, AT* sP, AT* sGD, AT (*sJ)[R::N])
 {
     using Mo = Model<DIMV>;
     using G = typename Mo::G;
     using HR = Halo1<Mo, DIMV>;
-    void* Pl = cs.P[t.step & 1];
     const Slots<AT> Js = slots<AT>(cs.J, cs.N);
     // fixed trip count, fully unrolled: every halo load is issued before the
     // first LDS write waits on one
@@ -708,7 +713,7 @@ __device__ __forceinline__ void pressure_tile(CDesc& cs, const TileCtx& t, AT* s
         if (k >= R::N) break;
         int off[3], cr;
         const uint32_t m = HR::cell(cs, t, k, off, &cr);
-        sP[k] = *at_node<AT>(Pl, m);
+        sP[k] = *at_node<AT>(cs.Ps, m);
         // ghost pressure = P(mirror) + rho(x) g.(ghost - mirror): keep g.off
         if (WALL) sGD[k] = (AT)(cs.grav[0] * off[0] + cs.grav[1] * off[1] + cs.grav[2] * off[2]);
 #pragma unroll
@@ -746,7 +751,7 @@ __device__ __forceinline__ void pressure_tile(CDesc& cs, const TileCtx& t, AT* s
         su += G::w(i) * cu;
     }
     // rho_ref T (1 + omega) K summed = (1 + omega) rho_ref / rho * sum w (dP)
-    const double P = P0 + (double)*at_node<AT>(cs.S, n) + (1.0 + omega) * ra / rho * sk + omega * ra * su;
+    const double P = P0 + (1.0 + omega) * ra / rho * sk + omega * ra * su;
     *at_node<AT>(cs.P[(t.step + 1) & 1], n) = (AT)P;
 }
 

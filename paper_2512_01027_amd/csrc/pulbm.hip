@@ -56,7 +56,7 @@ int store_bytes(int store) { return store == PULBM_STORE_FP64 ? 8 : store == PUL
 int aux_bytes(int store) { return store == PULBM_STORE_FP64 ? 8 : 4; }
 
 struct Layout {
-    size_t h, g, P0, P1, phi0, phi1, J, S, M2, U, desc, tab, partial, diag, total;
+    size_t h, g, P0, P1, phi0, phi1, J, Ps, M2, U, desc, tab, partial, diag, total;
 };
 
 Layout make_layout(const pulbm_params& p)
@@ -74,7 +74,7 @@ Layout make_layout(const pulbm_params& p)
     L.phi0 = put(N * ab);
     L.phi1 = put(N * ab);
     L.J = put((size_t)dim * N * ab);
-    L.S = put(N * ab);
+    L.Ps = put(N * ab);
     L.M2 = put((size_t)nm * N * ab);
     L.U = put((size_t)dim * N * ab);
     L.desc = put(sizeof(CaseDev));
@@ -316,7 +316,7 @@ extern "C" int pulbm_create(const pulbm_params* p, void* dev_arena, size_t arena
     h.h = c->base + L.h; h.g = c->base + L.g;
     h.P[0] = c->base + L.P0; h.P[1] = c->base + L.P1;
     h.phi[0] = c->base + L.phi0; h.phi[1] = c->base + L.phi1;
-    h.J = c->base + L.J; h.S = c->base + L.S;
+    h.J = c->base + L.J; h.Ps = c->base + L.Ps;
     h.M2 = c->base + L.M2; h.U = c->base + L.U;
     h.rho_a = p->rho_light; h.rho_w = p->rho_heavy;
     h.tau_a = p->nu_light / kT + 0.5;

@@ -127,10 +127,10 @@ def _shift(q, c):
 
 @pytest.mark.parametrize("dim", [2, 3])
 def test_reconstruction_matches_compact_form(dim):
-    """P = rho_ref T sum g + sum_i w_i [Pold(x - c_i) - Pold(x)] - (rho - rho_ref) T D.u*,
-    u = u* - D P / rho, u* = sum g c: the paper's K_i / omega form collapses to
-    this when omega_max = rho_water / rho_air, because (1 + omega) rho_ref / rho
-    = 1 and sum_i w_i c_i q(x - c_i) = -T D q."""
+    """P = P* + sum_i w_i [P*(x - c_i) - P*(x)] - (rho - rho_ref) T D.u*, with
+    P* = rho_ref T sum g, u = u* - D P / rho, u* = sum g c: the paper's K_i /
+    omega form collapses to this when omega_max = rho_water / rho_air, because
+    (1 + omega) rho_ref / rho = 1 and sum_i w_i c_i q(x - c_i) = -T D q."""
     cfg, f = _droplet_case(dim)
     oc = oracle.OracleCase(cfg)
     oc.init_fields(*f)
@@ -149,11 +149,12 @@ def test_reconstruction_matches_compact_form(dim):
                 out[a] += wg[i] * c[a] * d
         return out / (2 * T)
 
-    # P first: u* = sum g c at x - c_i in the omega term, K from the previous P
+    # P first: u* = sum g c at x - c_i in the omega term, K from P* = rho_ref T sum g
     J = np.stack([np.tensordot(cg[:, a], g, axes=(0, 0)) for a in range(dim)])
-    Lsum = sum(wg[i] * (_shift(Pl, -c) - Pl) for i, c in enumerate(cg))
+    Ps = ra * T * g.sum(0)
+    Lsum = sum(wg[i] * (_shift(Ps, -c) - Ps) for i, c in enumerate(cg))
     divJ = sum(D(J[a])[a] for a in range(dim))
-    P = ra * T * g.sum(0) + Lsum - (rho - ra) * T * divJ
+    P = Ps + Lsum - (rho - ra) * T * divJ
     # then u with K of the new P
     DP = D(P)
     u = np.stack([J[a] - DP[a] / rho for a in range(dim)])
