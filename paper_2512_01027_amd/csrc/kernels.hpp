@@ -857,9 +857,9 @@ __device__ __forceinline__ void tile_gradients(const CT* sPhi, const CT* sRho, c
 }
 
 // --- collide + stream.  A tile first issues the loads of its own nodes'
-// incoming h (parked in LDS until the direction loop) and M2, together with
-// the halo loads of phi and u, so that their latencies overlap; then it takes
-// the gradients from LDS and collides one direction at a time.
+// incoming h (parked in LDS until the direction loop) and M2,
+// together with the halo loads of phi and u, so that their latencies overlap;
+// then it takes the gradients from LDS and collides one direction at a time.
 template <int DIMV, class S, bool WALL, class R>
 __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typename Codec<S>::CT* sPhi,
                                              typename Codec<S>::CT* sRho,
@@ -936,15 +936,16 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
             return (CT)H::w(j) * sPhi[k];
         }
     };
-    // rest direction, then opposite pairs; both lattices share the direction
-    // order, so h_i and g_i stream to the same node
+    // rest direction of g, the opposite pairs, then the rest direction of h;
+    // both lattices share the direction order, so h_i and g_i stream to the
+    // same node
     {
         const CT g0 = g_out<G, DIMV, false>(v, kc, 0);
         aa_store<G, WALL, nt_access<S, kStoreCollide>()>(gs, nb, nv, 0, odd, Codec<S>::enc(g0, gsc, (CT)0), false);
-        const CT h0 = Codec<S>::dec(sH[0][threadIdx.x], hisc, php * (CT)H::w(0));
-        aa_store<H, WALL, nt_access<S, kStoreCollide>()>(hs, nb, nv, 0, odd,
-                          Codec<S>::enc(h_out<H, DIMV, false>(ph, v, kc, 0, h0), hsc, href(0, true)), false);
     }
+    // sum over j != 0 of the incoming h_j less the outgoing h*_j as its reader
+    // will decode it (the rest population balances it below)
+    CT hmoved = 0;
 #pragma unroll
     for (int i = 1; i < G::Q; i += 2) {
         const bool bi = WALL && nav_solid<G>(nv, i, +1);
@@ -970,10 +971,22 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
             const CT hk = Codec<S>::dec(sH[i + 1][threadIdx.x], hisc, php * (CT)H::w(i + 1));
             CT oi, ok;
             h_pair<H, DIMV, false>(ph, v, kc, i, hi, hk, &oi, &ok);
-            aa_store<H, WALL, nt_access<S, kStoreCollide>()>(hs, nb, nv, i, odd, Codec<S>::enc(oi, hsc, href(i, bi)), bi);
-            aa_store<H, WALL, nt_access<S, kStoreCollide>()>(hs, nb, nv, i + 1, odd,
-                                                             Codec<S>::enc(ok, hsc, href(i + 1, bk)), bk);
+            const CT ri = href(i, bi), rk = href(i + 1, bk);
+            const S ei = Codec<S>::enc(oi, hsc, ri), ek = Codec<S>::enc(ok, hsc, rk);
+            hmoved += (hi - Codec<S>::dec(ei, hisc, ri)) + (hk - Codec<S>::dec(ek, hisc, rk));
+            aa_store<H, WALL, nt_access<S, kStoreCollide>()>(hs, nb, nv, i, odd, ei, bi);
+            aa_store<H, WALL, nt_access<S, kStoreCollide>()>(hs, nb, nv, i + 1, odd, ek, bk);
         }
+    }
+    // rest population of h: BGK conserves phi (sum_j h^eq_j = phi), so
+    // h*_0 = h_0 + sum_{j != 0} (h_j - h*_j).  Taking it in that form, with the
+    // outgoing values as stored, keeps the weights' rounding (their FP32
+    // values sum to 1 + 1.5e-8 on D3Q19) and the rounding of identical bulk
+    // nodes from drifting phi's mass step after step.
+    {
+        const CT h0 = Codec<S>::dec(sH[0][threadIdx.x], hisc, php * (CT)H::w(0));
+        aa_store<H, WALL, nt_access<S, kStoreCollide>()>(hs, nb, nv, 0, odd,
+                                                         Codec<S>::enc(h0 + hmoved, hsc, href(0, true)), false);
     }
 }
 
@@ -1056,9 +1069,15 @@ __global__ __launch_bounds__(256) void k_init(CaseTab cases, const int* hdr,
     const CT hsc = (CT)cs.h_scale, gsc = (CT)cs.g_scale;
     // 2-byte storage: h_j - w_j phi0 (the previous-step phi of step 0 is phi0)
     const CT phr = sizeof(S) == 2 ? v.phi : (CT)0;
+    CT hmoved = 0;
 #pragma unroll
-    for (int j = 0; j < H::Q; ++j)
-        *hs.at(j, nb) = Codec<S>::enc(h_out<H, DIMV, true>(ph, v, kc, j, (CT)0), hsc, phr * (CT)H::w(j));
+    for (int j = 1; j < H::Q; ++j) {
+        const CT hj = h_out<H, DIMV, true>(ph, v, kc, j, (CT)0);
+        hmoved += hj;
+        *hs.at(j, nb) = Codec<S>::enc(hj, hsc, phr * (CT)H::w(j));
+    }
+    // rest population as the remainder, so that sum_j h_j = phi0 exactly
+    *hs.at(0, nb) = Codec<S>::enc(v.phi - hmoved, hsc, phr * (CT)H::w(0));
 #pragma unroll
     for (int i = 0; i < G::Q; ++i) *gs.at(i, nb) = Codec<S>::enc(g_out<G, DIMV, true>(v, kc, i), gsc, (CT)0);
     *at_node<CT>(cs.P[0], n) = (CT)P0[n];

@@ -163,6 +163,28 @@ def config_dam_break_3d(nx=512, ny=256, nz=256, store="fp16"):
     return cfg, (phi, P, u), 20000
 
 
+# Table I of Sec. III.D: surrounding fluid density, dynamic viscosities of
+# the surrounding fluid (1) and the bubble (2), surface tension.
+TABLE1 = {1: {"rho1": 2.2, "mu1": 7.3e-3, "mu2": 7.3e-4, "sigma": 3.0e-5},
+          2: {"rho1": 220.0, "mu1": 7.3e-1, "mu2": 7.3e-3, "sigma": 2.4e-4}}
+
+
+def config_table1_bubble(case, store="fp64"):
+    """2D rising bubble of Sec. III.D, Table I: 200 x 400, bubble R = 50 at
+    (100, 100), g = 1.36e-8 along -y, bubble density 0.22; no-slip walls on
+    all sides (the paper names no boundary conditions; the benchmark's box is
+    closed).  Returns cfg, fields and the steps of one time unit
+    sqrt(2R / g)."""
+    t = TABLE1[case]
+    rho2 = 0.22
+    cfg = base_case(2, 200, 400, wall=(1, 1, 0), gravity=(0.0, -1.36e-8, 0.0), rho_heavy=t["rho1"],
+                    rho_light=rho2, nu_heavy=t["mu1"] / t["rho1"], nu_light=t["mu2"] / rho2,
+                    sigma=t["sigma"], W=4.0, store=store)
+    phi, P, u = droplet(cfg, 50.0, center=(100.0, 100.0, 0.0), heavy_inside=False)
+    unit = math.sqrt(2.0 * 50.0 / 1.36e-8)
+    return cfg, (phi, P, u), unit
+
+
 def serving_case(rng, store="fp16", max_nodes=None):
     """One request of the serving stream: 75% 3D (n log-uniform in [32, 192]),
     25% 2D (n log-uniform in [128, 1024]); static droplet or rising bubble;
