@@ -150,6 +150,46 @@ def serving_leg(n_cases=64, step_scale=0.1):
                        f"(seed 4) of at most 64^3 nodes, all at t=0")}
 
 
+def table1_leg(t_end=1.0, samples=4):
+    """The 2D rising bubble of Sec. III.D, Table I cases 1 and 2 (200 x 400,
+    FP32 storage) run to t_end time units of sqrt(2R/g), with the bubble's
+    centroid height, rise velocity / U_g (U_g = sqrt(2Rg)) and circularity at
+    equal intervals.  The benchmark's reference values are not available here:
+    these are reported, not compared."""
+    import torch
+
+    from paper_2512_01027_amd import analysis as A
+    from paper_2512_01027_amd import binding as B
+    from paper_2512_01027_amd import workloads as W
+
+    out = {}
+    for case in (1, 2):
+        cfg, f, unit = W.config_table1_bubble(case, "fp32")
+        ug = (2 * 50.0 * 1.36e-8) ** 0.5
+        c = B.Case(cfg)
+        c.init_fields(*f)
+        c.sync()
+        n_total = int(round(t_end * unit))
+        marks = [int(round(n_total * (k + 1) / samples)) for k in range(samples)]
+        series, done, busy = [], 0, 0.0
+        for m in marks:
+            t0 = time.perf_counter()
+            c.step(m - done)
+            c.sync()
+            torch.cuda.synchronize()
+            busy += time.perf_counter() - t0
+            done = m
+            phi, _, u = c.read_fields()
+            series.append({"t": round(m / unit, 4), "centroid_y": round(A.centroid(phi[0])[1], 3),
+                           "rise_velocity_over_Ug": round(A.rise_velocity(phi[0], u[:, 0])[1] / ug, 4),
+                           "circularity": round(A.circularity(phi[0]), 4)})
+        d = c.diagnostics(allow_diverged=True)
+        c.close()
+        out[f"case{case}"] = {"steps": n_total, "MLUPS": round(cfg["nx"] * cfg["ny"] * n_total / busy / 1e6, 1),
+                              "nonfinite": d["nonfinite"], "series": series}
+    return out
+
+
 def cpu_baseline(cfg, fields):
     import oracle
 
@@ -176,6 +216,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp16", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-table1", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -235,6 +276,8 @@ def main():
                              "effective_GBs": round(m16 * 1e6 * state_bytes(2) / 1e9, 1)}
         if not args.no_serving:
             out["serving"] = serving_leg()
+    if not args.no_table1:
+        out["table1_rising_bubble"] = table1_leg()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, fields)
     print(json.dumps(out))
