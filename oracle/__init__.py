@@ -28,7 +28,7 @@ class Params(C.Structure):
     _fields_ = [
         ("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
         ("q_hydro", C.c_int32), ("q_phase", C.c_int32),
-        ("wall", C.c_int32 * 3), ("delta_theta", C.c_int32),
+        ("wall", C.c_int32 * 3), ("delta_theta", C.c_int32), ("collision", C.c_int32),
         ("rho_heavy", C.c_double), ("rho_light", C.c_double),
         ("nu_heavy", C.c_double), ("nu_light", C.c_double),
         ("sigma", C.c_double), ("W", C.c_double), ("M", C.c_double),
@@ -90,6 +90,7 @@ def make_params(cfg: dict) -> Params:
     for a in range(3):
         p.wall[a] = int(w[a])
     p.delta_theta = int(cfg.get("delta_theta", 1))
+    p.collision = {"filter": 0, "bgk": 1}[cfg.get("collision", "filter")]
     p.rho_heavy = float(cfg["rho_heavy"])
     p.rho_light = float(cfg["rho_light"])
     p.nu_heavy = float(cfg["nu_heavy"])

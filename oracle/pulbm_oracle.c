@@ -132,6 +132,7 @@ static int model_init(model* m, const pulbm_oracle_params* p)
     if (p->nx < 1 || p->ny < 1 || p->nz < 1 || (p->dim == 2 && p->nz != 1)) return -1;
     if (!(p->rho_heavy > 0) || !(p->rho_light > 0) || !(p->W > 0) || !(p->M > 0)) return -1;
     if (!(p->nu_heavy > 0) || !(p->nu_light > 0) || p->rho_heavy == p->rho_light) return -1;
+    if (p->collision != 0 && p->collision != 1) return -1;
     if (build_lattice(&m->G, p->dim, p->q_hydro)) return -1;
     if (build_lattice(&m->H, p->dim, p->q_phase)) return -1;
     m->p = *p;
@@ -460,14 +461,21 @@ static void collide_stream(pulbm_oracle_case* C)
                     hs[j] = hj - (hj - heq[j]) / M->tau_phi;
                 }
                 /* Filter collision (Eq. LB_filter_col): Pi from Eq. momentum_flux,
-                 * Phi_i from Eq. momentum_flux0. */
+                 * Phi_i from Eq. momentum_flux0; or the BGK collision of
+                 * Eq. BGK_LBeq_hydroeq with tau_mix. */
+                double gs[27];
+                if (M->p.collision == 1) {
+                    for (int i = 0; i < G->q; ++i) {
+                        double gi = C->g[(size_t)i * N + n];
+                        gs[i] = gi - (gi - geq[i]) / tau;
+                    }
+                } else {
                 double Pi[3][3] = {{0}};
                 for (int k = 0; k < G->q; ++k) {
                     double ne = C->g[(size_t)k * N + n] - geq[k];
                     for (int a = 0; a < dim; ++a)
                         for (int b = 0; b < dim; ++b) Pi[a][b] += G->c[k][a] * G->c[k][b] * ne;
                 }
-                double gs[27];
                 for (int i = 0; i < G->q; ++i) {
                     double phipi = 0.0;
                     for (int a = 0; a < dim; ++a)
@@ -477,6 +485,7 @@ static void collide_stream(pulbm_oracle_case* C)
                             phipi += phab * Pi[a][b];
                         }
                     gs[i] = geq[i] + (1.0 - 1.0 / tau) * phipi;
+                }
                 }
                 /* Streaming: push to x + c; at a wall, reflect into the opposite slot. */
                 for (int j = 0; j < H->q; ++j) {

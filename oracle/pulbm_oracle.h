@@ -28,6 +28,8 @@ typedef struct {
     int32_t q_hydro, q_phase;     /* 2D: 9/9; 3D: hydro 19|27, phase 19|27         */
     int32_t wall[3];              /* per axis: 0 periodic, 1 halfway bounce-back   */
     int32_t delta_theta;          /* 1: apply the anti-rarefaction correction      */
+    int32_t collision;            /* hydro collision: 0 filter (Eq. LB_filter_col),
+                                     1 BGK (Eq. BGK_LBeq_hydroeq)                  */
     double rho_heavy, rho_light;  /* phi = 1 fluid ("water"), phi = 0 fluid ("air") */
     double nu_heavy, nu_light;    /* kinematic viscosities                         */
     double sigma, W, M;           /* surface tension, interface width, mobility    */
