@@ -60,7 +60,9 @@ typedef struct {
     int32_t wall[3];             /* per axis: 0 periodic, 1 no-slip walls at both ends      */
     int32_t delta_theta;         /* 1: apply the delta-theta correction of Sec. II [1]      */
     int32_t store;               /* PULBM_STORE_*                                           */
-    int32_t reserved;            /* must be 0                                               */
+    int32_t collision;           /* hydrodynamic collision: 0 the filter collision of Sec. II
+                                    (Eq. LB_filter_col) [0]; 1 BGK with tau_mix (Eq.
+                                    BGK_LBeq_hydroeq; less robust at high density ratio)    */
     double rho_heavy, rho_light; /* densities of the phi = 1 and phi = 0 fluids              */
     double nu_heavy, nu_light;   /* kinematic viscosities (> 0)                             */
     double sigma, W, M;          /* surface tension, interface width, mobility [M = 0.166]  */

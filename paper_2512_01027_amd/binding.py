@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libpulbm.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, EDIVERGED, ESTATE, EAGAIN = 0, -1, -2, -3, -4, -5, -6
 STORES = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3}
+COLLISIONS = {"filter": 0, "bgk": 1}
 
 EXPORTS = [
     "pulbm_required_bytes", "pulbm_create", "pulbm_init_fields", "pulbm_step", "pulbm_step_timed",
@@ -39,7 +40,7 @@ class Params(C.Structure):
     _fields_ = [
         ("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
         ("q_hydro", C.c_int32), ("q_phase", C.c_int32), ("wall", C.c_int32 * 3),
-        ("delta_theta", C.c_int32), ("store", C.c_int32), ("reserved", C.c_int32),
+        ("delta_theta", C.c_int32), ("store", C.c_int32), ("collision", C.c_int32),
         ("rho_heavy", C.c_double), ("rho_light", C.c_double),
         ("nu_heavy", C.c_double), ("nu_light", C.c_double),
         ("sigma", C.c_double), ("W", C.c_double), ("M", C.c_double),
@@ -131,7 +132,8 @@ def make_params(cfg: dict) -> Params:
     p.delta_theta = int(cfg.get("delta_theta", 1))
     st = cfg.get("store", "fp64")
     p.store = STORES[st] if isinstance(st, str) else int(st)
-    p.reserved = 0
+    coll = cfg.get("collision", "filter")
+    p.collision = COLLISIONS[coll] if isinstance(coll, str) else int(coll)
     p.rho_heavy = float(cfg["rho_heavy"])
     p.rho_light = float(cfg["rho_light"])
     p.nu_heavy = float(cfg["nu_heavy"])

@@ -860,7 +860,7 @@ __device__ __forceinline__ void tile_gradients(const CT* sPhi, const CT* sRho, c
 // incoming h (parked in LDS until the direction loop) and M2,
 // together with the halo loads of phi and u, so that their latencies overlap;
 // then it takes the gradients from LDS and collides one direction at a time.
-template <int DIMV, class S, bool WALL, class R>
+template <int DIMV, class S, bool WALL, bool BGK, class R>
 __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typename Codec<S>::CT* sPhi,
                                              typename Codec<S>::CT* sRho,
                                              typename Codec<S>::CT (*sU)[R::N], S (*sH)[256])
@@ -885,13 +885,19 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
     S hraw[H::Q];
     CT m2[NM];
     CT php = 0;  // reference of the incoming h (2-byte storage)
+    CT dP = 0;   // BGK: (previous P - new P) / (rho_ref T), restores the stored rest population
     if (inside) {
         php = h_reference<S>(cs.phi[(t.step + 1) & 1], n);
 #pragma unroll
         for (int j = 0; j < H::Q; ++j) hraw[j] = aa_load<H, WALL, nt_access<S, kLoadCollide>()>(hs, nb, nv, j, odd);
-        const Slots<CT> Ms = slots<CT>(cs.M2, cs.N);
+        if constexpr (BGK) {
+            dP = (CT)(((double)*at_node<CT>(cs.P[t.step & 1], n) - (double)*at_node<CT>(cs.P[(t.step + 1) & 1], n)) *
+                      (3.0 / cs.rho_a));
+        } else {
+            const Slots<CT> Ms = slots<CT>(cs.M2, cs.N);
 #pragma unroll
-        for (int k = 0; k < NM; ++k) m2[k] = *Ms.at(k, na);
+            for (int k = 0; k < NM; ++k) m2[k] = *Ms.at(k, na);
+        }
     }
     // halo of phi, rho and u
     const Slots<CT> Us = slots<CT>(cs.U, cs.N);
@@ -921,8 +927,10 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
 
     NodeVals<CT> v;
     tile_gradients<DIMV, R, CT>(sPhi, sRho, sU, lx + 1, ly + 1, lz + HR::ZH, v);
-    const NodeCoef<DIMV, CT> kc = node_coef<DIMV, false, CT>(ph, v, m2);
-    const CT hisc = (CT)cs.h_inv_scale, hsc = (CT)cs.h_scale, gsc = (CT)cs.g_scale;
+    // the BGK collision needs the equilibria alone (no Pi: the INIT form)
+    const NodeCoef<DIMV, CT> kc = node_coef<DIMV, BGK, CT>(ph, v, m2);
+    const CT omf = BGK ? (CT)1 - rcp(ph.tau_a + clamp01(v.phi) * ph.dtau) : (CT)0;  // 1 - 1/tau_mix
+    const CT hisc = (CT)cs.h_inv_scale, hsc = (CT)cs.h_scale, gsc = (CT)cs.g_scale, gsc_in = (CT)cs.g_inv_scale;
     const CT corr = (CT)6.0 * rcp(kc.rho);  // 2 / (rho T)
     // reference of an outgoing h_j in 2-byte storage: w_j phi (this step) of
     // the node that reads it next step -- x + c_j, or x itself for a
@@ -940,7 +948,13 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
     // both lattices share the direction order, so h_i and g_i stream to the
     // same node
     {
-        const CT g0 = g_out<G, DIMV, false>(v, kc, 0);
+        CT g0 = g_out<G, DIMV, BGK>(v, kc, 0);
+        if constexpr (BGK) {
+            // BGK (Eq. BGK_LBeq_hydroeq) on the full rest population; both the
+            // stored incoming value and the equilibrium lack their P / (rho_ref T)
+            const CT gin = Codec<S>::dec(aa_load<G, WALL, false>(gs, nb, nv, 0, odd), gsc_in, (CT)0) + dP;
+            g0 += omf * (gin - g0);
+        }
         aa_store<G, WALL, nt_access<S, kStoreCollide>()>(gs, nb, nv, 0, odd, Codec<S>::enc(g0, gsc, (CT)0), false);
     }
     // sum over j != 0 of the incoming h_j less the outgoing h*_j as its reader
@@ -951,7 +965,15 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
         const bool bi = WALL && nav_solid<G>(nv, i, +1);
         const bool bk = WALL && nav_solid<G>(nv, i + 1, +1);
         CT gi, gk;
-        g_pair<G, DIMV, false>(v, kc, i, &gi, &gk);
+        g_pair<G, DIMV, BGK>(v, kc, i, &gi, &gk);
+        if constexpr (BGK) {
+            // incoming g_i, g_i+1: within a step a node reads and writes one set
+            // of slots (AA), and the slots of this pair are written just below
+            const CT ai = Codec<S>::dec(aa_load<G, WALL, false>(gs, nb, nv, i, odd), gsc_in, (CT)0);
+            const CT ak = Codec<S>::dec(aa_load<G, WALL, false>(gs, nb, nv, i + 1, odd), gsc_in, (CT)0);
+            gi += omf * (ai - gi);
+            gk += omf * (ak - gk);
+        }
         if (WALL) {
             CT cF = 0;
 #pragma unroll
@@ -990,7 +1012,6 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
     }
 }
 
-template <int DIMV, class S>
 // Occupancy target of the collision kernel in waves per SIMD (0 leaves the
 // register budget to the compiler).  Left alone the compiler takes ~175-195
 // VGPRs (2 waves); a budget of 168 (3 waves) costs a few dwords of spill and
@@ -1004,6 +1025,7 @@ template <int DIMV, class S>
 #else
 #define PULBM_COLLIDE_ATTR
 #endif
+template <int DIMV, class S, bool BGK>
 __global__ __launch_bounds__(256) PULBM_COLLIDE_ATTR void k_collide(CaseTab cases, const int* hdr, int step_off)
 {
     using Mo = Model<DIMV>;
@@ -1015,8 +1037,8 @@ __global__ __launch_bounds__(256) PULBM_COLLIDE_ATTR void k_collide(CaseTab case
     const TileCtx t = tile_ctx<Mo>(cases, hdr, step_off);
     if (!t.active) return;
     CDesc& cs = *t.cs;
-    if (tile_at_wall<Mo>(cs, t.ox, t.oy, t.oz)) collide_tile<DIMV, S, true, R>(cs, t, sPhi, sRho, sU, sH);
-    else collide_tile<DIMV, S, false, R>(cs, t, sPhi, sRho, sU, sH);
+    if (tile_at_wall<Mo>(cs, t.ox, t.oy, t.oz)) collide_tile<DIMV, S, true, BGK, R>(cs, t, sPhi, sRho, sU, sH);
+    else collide_tile<DIMV, S, false, BGK, R>(cs, t, sPhi, sRho, sU, sH);
 }
 
 // --- initial state: equilibria of (phi0, P0, u0) in the even AA layout,

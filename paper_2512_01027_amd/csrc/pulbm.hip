@@ -103,7 +103,8 @@ int validate(const pulbm_params* p)
     if (nodes * widest >= 2147483648.0)
         return fail(PULBM_EINVAL, "grid too large: %.0f nodes x %d bytes per field element must stay below 2^31",
                     nodes, widest);
-    if (p->reserved != 0) return fail(PULBM_EINVAL, "reserved field must be 0");
+    if (p->collision != 0 && p->collision != 1)
+        return fail(PULBM_EINVAL, "collision must be 0 (filter) or 1 (BGK)");
     for (int a = 0; a < 3; ++a)
         if (p->wall[a] != 0 && p->wall[a] != 1) return fail(PULBM_EINVAL, "wall[%d] must be 0 or 1", a);
     if (p->dim == 2 && p->wall[2]) return fail(PULBM_EINVAL, "2D cases have no z walls");
@@ -153,34 +154,38 @@ struct pulbm_case {
 namespace {
 
 template <int DIMV, class S>
-void launch_step(hipStream_t st, CaseDev* const* tab, const int* hdr, int blocks, int off, int which)
+void launch_step(hipStream_t st, CaseDev* const* tab, const int* hdr, int blocks, int off, int which, bool bgk)
 {
     using CT = typename Codec<S>::CT;
     const dim3 grid(blocks), block(256);
     if (which == 0) hipLaunchKernelGGL((k_moments<DIMV, S>), grid, block, 0, st, tab, hdr, off);
     if (which == 1) hipLaunchKernelGGL((k_pressure<DIMV, CT>), grid, block, 0, st, tab, hdr, off);
     if (which == 2) hipLaunchKernelGGL((k_velocity<DIMV, CT>), grid, block, 0, st, tab, hdr, off);
-    if (which == 3) hipLaunchKernelGGL((k_collide<DIMV, S>), grid, block, 0, st, tab, hdr, off);
+    if (which == 3) {
+        if (bgk) hipLaunchKernelGGL((k_collide<DIMV, S, true>), grid, block, 0, st, tab, hdr, off);
+        else hipLaunchKernelGGL((k_collide<DIMV, S, false>), grid, block, 0, st, tab, hdr, off);
+    }
 }
 
 template <int DIMV>
-void launch_dim(int store, hipStream_t st, CaseDev* const* tab, const int* hdr, int blocks, int off, int which)
+void launch_dim(int store, hipStream_t st, CaseDev* const* tab, const int* hdr, int blocks, int off, int which,
+                bool bgk)
 {
     switch (store) {
-        case PULBM_STORE_FP64: launch_step<DIMV, double>(st, tab, hdr, blocks, off, which); break;
-        case PULBM_STORE_FP32: launch_step<DIMV, float>(st, tab, hdr, blocks, off, which); break;
-        case PULBM_STORE_FP16: launch_step<DIMV, _Float16>(st, tab, hdr, blocks, off, which); break;
-        default: launch_step<DIMV, uint16_t>(st, tab, hdr, blocks, off, which); break;
+        case PULBM_STORE_FP64: launch_step<DIMV, double>(st, tab, hdr, blocks, off, which, bgk); break;
+        case PULBM_STORE_FP32: launch_step<DIMV, float>(st, tab, hdr, blocks, off, which, bgk); break;
+        case PULBM_STORE_FP16: launch_step<DIMV, _Float16>(st, tab, hdr, blocks, off, which, bgk); break;
+        default: launch_step<DIMV, uint16_t>(st, tab, hdr, blocks, off, which, bgk); break;
     }
 }
 
 // which: 0 moments, 1 pressure, 2 velocity, 3 collide + stream.  blocks must
 // cover the table's tiles (rounded up to a multiple of 8); extra blocks exit.
-void launch(int dim, int store, hipStream_t st, CaseDev* const* tab, const int* hdr, int blocks, int off,
+void launch(int dim, int store, bool bgk, hipStream_t st, CaseDev* const* tab, const int* hdr, int blocks, int off,
             int which)
 {
-    if (dim == 2) launch_dim<2>(store, st, tab, hdr, blocks, off, which);
-    else launch_dim<3>(store, st, tab, hdr, blocks, off, which);
+    if (dim == 2) launch_dim<2>(store, st, tab, hdr, blocks, off, which, bgk);
+    else launch_dim<3>(store, st, tab, hdr, blocks, off, which, bgk);
 }
 
 template <int DIMV, class S>
@@ -233,7 +238,7 @@ int upload_desc(pulbm_case* c)
 int read_pass(pulbm_case* c)
 {
     for (int w = 0; w < kReadKernels; ++w)
-        launch(c->p.dim, c->p.store, c->stream, c->tab, c->hdr, grid_of(c->ntiles), -1, w);
+        launch(c->p.dim, c->p.store, c->p.collision == 1, c->stream, c->tab, c->hdr, grid_of(c->ntiles), -1, w);
     HIPC(hipGetLastError());
     return PULBM_OK;
 }
@@ -394,7 +399,7 @@ static void queue_direct(pulbm_case* c, int count)
 {
     for (int k = 0; k < count; ++k)
         for (int w = 0; w < kStepKernels; ++w)
-            launch(c->p.dim, c->p.store, c->stream, c->tab, c->hdr, grid_of(c->ntiles), k, w);
+            launch(c->p.dim, c->p.store, c->p.collision == 1, c->stream, c->tab, c->hdr, grid_of(c->ntiles), k, w);
     hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, c->stream, c->tab, c->hdr, count);
 }
 
@@ -430,7 +435,7 @@ extern "C" int pulbm_step_timed(pulbm_case* c, int64_t nsteps, double* ms)
     for (int64_t s = 0; s < nsteps && rc == PULBM_OK; ++s) {
         (void)hipEventRecord(ev[0], c->stream);
         for (int w = 0; w < kStepKernels; ++w) {
-            launch(c->p.dim, c->p.store, c->stream, c->tab, c->hdr, grid_of(c->ntiles), 0, w);
+            launch(c->p.dim, c->p.store, c->p.collision == 1, c->stream, c->tab, c->hdr, grid_of(c->ntiles), 0, w);
             (void)hipEventRecord(ev[w + 1], c->stream);
         }
         hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, c->stream, c->tab, c->hdr, 1);
@@ -629,7 +634,7 @@ struct pulbm_batch {
         int which = 0;
         int cap = 0, ncases = 0, tiles = 0, grid = 0;
         std::map<int, hipGraphExec_t> graphs;  // by ksteps, captured for `grid` blocks
-    } tab[2];
+    } tab[4];  // index (dim - 2) + 2 * collision
     bool dirty = true;
 };
 
@@ -715,8 +720,8 @@ void drop_graphs(pulbm_batch* b, pulbm_batch::Tab& t)
 
 int rebuild_tables(pulbm_batch* b)
 {
-    for (int di = 0; di < 2; ++di) {
-        const int dim = di + 2;
+    for (int di = 0; di < 4; ++di) {
+        const int dim = (di & 1) + 2, coll = di >> 1;
         pulbm_batch::Tab& t = b->tab[di];
         if (t.cap == 0) {  // sized once for every slot
             t.cap = b->max_slots;
@@ -735,7 +740,7 @@ int rebuild_tables(pulbm_batch* b)
         int n = 0;
         hdr[2] = 0;
         for (auto& s : b->slots)
-            if (s.c && s.c->p.dim == dim) {
+            if (s.c && s.c->p.dim == dim && s.c->p.collision == coll) {
                 ptr[n] = s.c->d;
                 hdr[3 + n] = hdr[2 + n] + s.c->ntiles;
                 ++n;
@@ -852,7 +857,7 @@ extern "C" int pulbm_batch_advance(pulbm_batch* b, int32_t ksteps)
     int rc = sync_advances(b, 0);
     if (rc) return rc;
     if (b->dirty && (rc = rebuild_tables(b))) return rc;
-    for (int di = 0; di < 2; ++di) {
+    for (int di = 0; di < 4; ++di) {
         pulbm_batch::Tab& t = b->tab[di];
         if (t.ncases == 0) continue;
         auto it = t.graphs.find(ksteps);
@@ -862,7 +867,7 @@ extern "C" int pulbm_batch_advance(pulbm_batch* b, int32_t ksteps)
             HIPC(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
             for (int k = 0; k < ksteps; ++k)
                 for (int w = 0; w < kStepKernels; ++w)
-                    launch(di + 2, b->store, b->stream, t.dtab, t.dhdr, t.grid, k, w);
+                    launch((di & 1) + 2, b->store, (di >> 1) == 1, b->stream, t.dtab, t.dhdr, t.grid, k, w);
             hipLaunchKernelGGL(k_advance, dim3((t.cap + 63) / 64), dim3(64), 0, b->stream, t.dtab, t.dhdr, ksteps);
             HIPC(hipStreamEndCapture(b->stream, &g));
             HIPC(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));

@@ -105,7 +105,7 @@ def test_required_bytes_scales_with_store(lib):
     (dict(nz=2), "nz = 1"),                   # 2D with nz != 1
     (dict(nx=0), ""),                         # empty grid
     (dict(q_hydro=27), ""),                   # wrong lattice for 2D
-    (dict(reserved=1), ""),
+    (dict(collision=2), "collision"),
     (dict(store=7), ""),
     (dict(nu_light=0.0), "viscosities"),
     (dict(rho_light=2000.0), "densities"),

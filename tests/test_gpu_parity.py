@@ -216,3 +216,23 @@ def test_graph_replay_equals_direct_launches(store):
     assert a.steps_done == b.steps_done == 100
     for x, y in zip(a.read_fields(), b.read_fields()):
         assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("store,tol", [("fp64", TOL64), ("fp32", 2e-5)])
+@pytest.mark.parametrize("case", ["2d_walls_gravity", "3d_periodic_ragged", "3d_all_walls"])
+def test_bgk_collision_matches_oracle(case, store, tol):
+    """The BGK hydrodynamic collision (Eq. BGK_LBeq_hydroeq, collision = 1)
+    at nu = 0.1, where it is stable at density ratio 1000."""
+    kw = dict(CASES[case])
+    dim, nx, ny = kw.pop("dim"), kw.pop("nx"), kw.pop("ny")
+    nz = kw.pop("nz", 1)
+    cfg = W.base_case(dim, nx, ny, nz, nu_heavy=0.1, nu_light=0.1, store=store, collision="bgk", **kw)
+    f = _fields(cfg)
+    g = B.Case(cfg)
+    g.init_fields(*f)
+    o = oracle.OracleCase(dict(cfg, store="fp64"))
+    o.init_fields(*f)
+    for s in (1, 6, 23):
+        g.step(s)
+        o.step(s)
+        _compare(g.read_fields(), o.read_fields(), tol, f"{case} bgk {store} +{s}")

@@ -1,7 +1,8 @@
 """Serving batch: many resident cases advanced together.
 
 - each case's result is bitwise the same alone (the single-case API), alone
-  in a batch and in a mix of 2D and 3D cases of other sizes and step counts,
+  in a batch and in a mix of 2D and 3D cases of other sizes, step counts and
+  collision operators,
   including a case admitted while the others are part-way through;
 - each case runs exactly its requested number of steps, whatever the advance
   granularity;
@@ -28,7 +29,9 @@ def _cases(store):
     fc = W.droplet(c, 4.0, center=(10.0, 8.0, 4.0), heavy_inside=False)
     d = W.base_case(2, 37, 29, store=store, rho_heavy=10.0)
     fd = W.droplet(d, 8.0)
-    return [(a, fa, 37), (b, fb, 50), (c, fc, 23), (d, fd, 41)]
+    e = W.base_case(3, 18, 14, 10, store=store, nu_heavy=0.1, nu_light=0.1, collision="bgk")
+    fe = W.droplet(e, 4.0)
+    return [(a, fa, 37), (b, fb, 50), (c, fc, 23), (d, fd, 41), (e, fe, 29)]
 
 
 def _alone(cfg, f, n):
@@ -49,9 +52,10 @@ def test_alone_equals_mix_bitwise(store):
     cases = _cases(store)
     ref = [_alone(cfg, f, n) for cfg, f, n in cases]
     bt = B.Batch(1 << 30, store=store, max_slots=8)
-    # the first three start together; the fourth arrives after 16 steps
+    # the first three and the BGK case start together; the fourth arrives
+    # after 16 steps
     slots = {}
-    for k in range(3):
+    for k in (0, 1, 2, 4):
         cfg, f, n = cases[k]
         slots[bt.admit(cfg, *f, n)] = k
     got = {}
