@@ -16,6 +16,8 @@ Printed as one JSON line:
   hbm            state bytes per node-update x MLUPS, against the peak and
                  against a device copy measured here
   fp16_store     the same workload with FP16 storage
+  d3q19_hydro    the same workload on D3Q19 for the hydrodynamic populations
+                 too (the lattice of the paper's 3D runs), FP32 and FP16
   serving        a seeded Poisson stream of droplet / bubble requests served
                  by continuous batching, p50 / p99 latency and aggregate MLUPS,
                  beside the same stream run one case at a time
@@ -40,24 +42,25 @@ COUNTERS = os.path.join(ROOT, "profiles", "galilean_droplet_128cube_hbm_counters
 # and writes phi, u*(3), S, M2(6); pressure reads u*(3), P, phi, S and writes
 # P; velocity reads P, u*(3), phi and writes u(3); collide reads phi, u(3),
 # M2(6), h(19) and writes 46 populations.  2-byte storage also reads the
-# previous-step phi in moments and collide (the h codec's reference).
+# previous-step phi in moments and collide (the h codec's reference).  With
+# D3Q19 hydro the populations per node are 38.
 POP_VALUES_3D = 46
 KERNELS = ("moments", "pressure", "velocity", "collide")
 
 
-def kernel_bytes(store_bytes, aux_bytes=4):
+def kernel_bytes(store_bytes, aux_bytes=4, pops=POP_VALUES_3D):
     ref = aux_bytes if store_bytes == 2 else 0
     return {
-        "moments": POP_VALUES_3D * store_bytes + ref + 11 * aux_bytes,
+        "moments": pops * store_bytes + ref + 11 * aux_bytes,
         "pressure": 7 * aux_bytes,
         "velocity": 8 * aux_bytes,
-        "collide": 19 * store_bytes + ref + 10 * aux_bytes + POP_VALUES_3D * store_bytes,
+        "collide": 19 * store_bytes + ref + 10 * aux_bytes + pops * store_bytes,
     }
 
 
-def state_bytes(store_bytes, aux_bytes=4):
-    """Read and write of the state (46 populations and the pressure) once."""
-    return 2 * (POP_VALUES_3D * store_bytes + aux_bytes)
+def state_bytes(store_bytes, aux_bytes=4, pops=POP_VALUES_3D):
+    """Read and write of the state (the populations and the pressure) once."""
+    return 2 * (pops * store_bytes + aux_bytes)
 
 
 def run_gpu(cfg, fields, steps, warmup):
@@ -217,6 +220,7 @@ def main():
     ap.add_argument("--no-fp16", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-table1", action="store_true")
+    ap.add_argument("--no-d3q19", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -276,6 +280,18 @@ def main():
                              "effective_GBs": round(m16 * 1e6 * state_bytes(2) / 1e9, 1)}
         if not args.no_serving:
             out["serving"] = serving_leg()
+    if not args.no_d3q19:
+        leg = {}
+        for store, sb in (("fp32", 4), ("fp16", 2)):
+            d19, ms19, dg19 = run_gpu(dict(cfg, store=store, q_hydro=19), fields, args.steps, args.warmup)
+            kb19 = kernel_bytes(sb, pops=38)
+            m19 = N * args.steps / d19 / 1e6
+            leg[store] = {"value": round(m19, 2), "unit": "MLUPS",
+                          "kernel_ms": {k: round(float(v), 4) for k, v in zip(KERNELS, ms19)},
+                          "collide_GBs": round(kb19["collide"] * N / (ms19[3] * 1e-3) / 1e9, 1),
+                          "effective_GBs": round(m19 * 1e6 * state_bytes(sb, pops=38) / 1e9, 1),
+                          "nonfinite": dg19["nonfinite"]}
+        out["d3q19_hydro"] = leg
     if not args.no_table1:
         out["table1_rising_bubble"] = table1_leg()
     if not args.no_cpu:

@@ -56,7 +56,8 @@ extern "C" {
 typedef struct {
     int32_t dim, nx, ny, nz;     /* dim 2 (nz = 1) or 3; every n >= 1; nx*ny*nz below 2^28
                                     nodes in FP64 storage, below 2^29 otherwise             */
-    int32_t q_hydro, q_phase;    /* 2D: 9, 9; 3D: 27, 19 (hydro D3Q27, phase field D3Q19)   */
+    int32_t q_hydro, q_phase;    /* 2D: 9, 9; 3D: 27 or 19, 19 (hydro D3Q27, or D3Q19 as the
+                                    paper's 3D runs; phase field D3Q19)                      */
     int32_t wall[3];             /* per axis: 0 periodic, 1 no-slip walls at both ends      */
     int32_t delta_theta;         /* 1: apply the delta-theta correction of Sec. II [1]      */
     int32_t store;               /* PULBM_STORE_*                                           */

@@ -618,10 +618,11 @@ __device__ __forceinline__ CT h_reference(void* phi_prev, uint32_t n)
 }
 
 // --- moments: phi, u* = sum g c, P*, M2 (per node; no halo)
-template <int DIMV, class S, bool WALL>
+template <int LS, class S, bool WALL>
 __device__ __forceinline__ void moments_node(CDesc& cs, int x, int y, int z, bool odd)
 {
-    using Mo = Model<DIMV>;
+    constexpr int DIMV = Model<LS>::DIM;
+    using Mo = Model<LS>;
     using G = typename Mo::G;
     using H = typename Mo::H;
     using CT = typename Codec<S>::CT;
@@ -676,10 +677,11 @@ __device__ __forceinline__ void moments_node(CDesc& cs, int x, int y, int z, boo
     for (int k = 0; k < NM; ++k) *Ms.at(k, na) = m2[k];
 }
 
-template <int DIMV, class S>
+template <int LS, class S>
 __global__ __launch_bounds__(256) void k_moments(CaseTab cases, const int* hdr, int step_off)
 {
-    using Mo = Model<DIMV>;
+    constexpr int DIMV = Model<LS>::DIM;
+    using Mo = Model<LS>;
     const TileCtx t = tile_ctx<Mo>(cases, hdr, step_off);
     if (!t.active) return;
     CDesc& cs = *t.cs;
@@ -688,8 +690,8 @@ __global__ __launch_bounds__(256) void k_moments(CaseTab cases, const int* hdr, 
     const int x = t.ox + lx, y = t.oy + ly, z = t.oz + lz;
     if (x >= cs.nx || y >= cs.ny || z >= cs.nz) return;
     const bool odd = t.step & 1;
-    if (tile_at_wall<Mo>(cs, t.ox, t.oy, t.oz)) moments_node<DIMV, S, true>(cs, x, y, z, odd);
-    else moments_node<DIMV, S, false>(cs, x, y, z, odd);
+    if (tile_at_wall<Mo>(cs, t.ox, t.oy, t.oz)) moments_node<LS, S, true>(cs, x, y, z, odd);
+    else moments_node<LS, S, false>(cs, x, y, z, odd);
 }
 
 // --- pressure (Sec. II): P = rho_ref T sum_i (g_i + (1 + omega) K_i)
@@ -698,10 +700,11 @@ __global__ __launch_bounds__(256) void k_moments(CaseTab cases, const int* hdr, 
 //     pressure the streamed populations carry, P* = rho_ref T sum g: K_i from
 //     P*.  FP64 arithmetic whatever the storage precision; the tile is staged
 //     in LDS in the storage type (exact) and widened at use.
-template <int DIMV, class AT, bool WALL, class R>
+template <int LS, class AT, bool WALL, class R>
 __device__ __forceinline__ void pressure_tile(CDesc& cs, const TileCtx& t, AT* sP, AT* sGD, AT (*sJ)[R::N])
 {
-    using Mo = Model<DIMV>;
+    constexpr int DIMV = Model<LS>::DIM;
+    using Mo = Model<LS>;
     using G = typename Mo::G;
     using HR = Halo1<Mo, DIMV>;
     const Slots<AT> Js = slots<AT>(cs.J, cs.N);
@@ -755,24 +758,26 @@ __device__ __forceinline__ void pressure_tile(CDesc& cs, const TileCtx& t, AT* s
     *at_node<AT>(cs.P[(t.step + 1) & 1], n) = (AT)P;
 }
 
-template <int DIMV, class AT>
+template <int LS, class AT>
 __global__ __launch_bounds__(256) void k_pressure(CaseTab cases, const int* hdr, int step_off)
 {
-    using Mo = Model<DIMV>;
+    constexpr int DIMV = Model<LS>::DIM;
+    using Mo = Model<LS>;
     using R = typename Halo1<Mo, DIMV>::R;
     __shared__ AT sP[R::N], sGD[R::N], sJ[DIMV][R::N];
     const TileCtx t = tile_ctx<Mo>(cases, hdr, step_off);
     if (!t.active) return;
     CDesc& cs = *t.cs;
-    if (tile_at_wall<Mo>(cs, t.ox, t.oy, t.oz)) pressure_tile<DIMV, AT, true, R>(cs, t, sP, sGD, sJ);
-    else pressure_tile<DIMV, AT, false, R>(cs, t, sP, sGD, sJ);
+    if (tile_at_wall<Mo>(cs, t.ox, t.oy, t.oz)) pressure_tile<LS, AT, true, R>(cs, t, sP, sGD, sJ);
+    else pressure_tile<LS, AT, false, R>(cs, t, sP, sGD, sJ);
 }
 
 // --- velocity: u = u* + sum_i K_i c_i with K_i of the new pressure.
-template <int DIMV, class CT, bool WALL, class R>
+template <int LS, class CT, bool WALL, class R>
 __device__ __forceinline__ void velocity_tile(CDesc& cs, const TileCtx& t, CT* sP, CT* sGD)
 {
-    using Mo = Model<DIMV>;
+    constexpr int DIMV = Model<LS>::DIM;
+    using Mo = Model<LS>;
     using G = typename Mo::G;
     using HR = Halo1<Mo, DIMV>;
     void* Pn = cs.P[(t.step + 1) & 1];
@@ -815,25 +820,27 @@ __device__ __forceinline__ void velocity_tile(CDesc& cs, const TileCtx& t, CT* s
     for (int a = 0; a < DIMV; ++a) *Us.at(a, na) = *Js.at(a, na) - gr[a] * (CT)3.0 * irho;
 }
 
-template <int DIMV, class CT>
+template <int LS, class CT>
 __global__ __launch_bounds__(256) void k_velocity(CaseTab cases, const int* hdr, int step_off)
 {
-    using Mo = Model<DIMV>;
+    constexpr int DIMV = Model<LS>::DIM;
+    using Mo = Model<LS>;
     using R = typename Halo1<Mo, DIMV>::R;
     __shared__ CT sP[R::N], sGD[R::N];
     const TileCtx t = tile_ctx<Mo>(cases, hdr, step_off);
     if (!t.active) return;
     CDesc& cs = *t.cs;
-    if (tile_at_wall<Mo>(cs, t.ox, t.oy, t.oz)) velocity_tile<DIMV, CT, true, R>(cs, t, sP, sGD);
-    else velocity_tile<DIMV, CT, false, R>(cs, t, sP, sGD);
+    if (tile_at_wall<Mo>(cs, t.ox, t.oy, t.oz)) velocity_tile<LS, CT, true, R>(cs, t, sP, sGD);
+    else velocity_tile<LS, CT, false, R>(cs, t, sP, sGD);
 }
 
 // Gradients of phi, rho and u at interior cell (cx, cy, cz) of a 1-halo tile.
-template <int DIMV, class R, class CT>
+template <int LS, class R, class CT>
 __device__ __forceinline__ void tile_gradients(const CT* sPhi, const CT* sRho, const CT (*sU)[R::N], int cx,
                                                int cy, int cz, NodeVals<CT>& v)
 {
-    using G = typename Model<DIMV>::G;
+    constexpr int DIMV = Model<LS>::DIM;
+    using G = typename Model<LS>::G;
     const int c0 = R::idx(cx, cy, cz);
     v.phi = sPhi[c0];
 #pragma unroll
@@ -860,12 +867,13 @@ __device__ __forceinline__ void tile_gradients(const CT* sPhi, const CT* sRho, c
 // incoming h (parked in LDS until the direction loop) and M2,
 // together with the halo loads of phi and u, so that their latencies overlap;
 // then it takes the gradients from LDS and collides one direction at a time.
-template <int DIMV, class S, bool WALL, bool BGK, class R>
+template <int LS, class S, bool WALL, bool BGK, class R>
 __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typename Codec<S>::CT* sPhi,
                                              typename Codec<S>::CT* sRho,
                                              typename Codec<S>::CT (*sU)[R::N], S (*sH)[256])
 {
-    using Mo = Model<DIMV>;
+    constexpr int DIMV = Model<LS>::DIM;
+    using Mo = Model<LS>;
     using G = typename Mo::G;
     using H = typename Mo::H;
     using CT = typename Codec<S>::CT;
@@ -926,7 +934,7 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
     if (!inside) return;
 
     NodeVals<CT> v;
-    tile_gradients<DIMV, R, CT>(sPhi, sRho, sU, lx + 1, ly + 1, lz + HR::ZH, v);
+    tile_gradients<LS, R, CT>(sPhi, sRho, sU, lx + 1, ly + 1, lz + HR::ZH, v);
     // the BGK collision needs the equilibria alone (no Pi: the INIT form)
     const NodeCoef<DIMV, CT> kc = node_coef<DIMV, BGK, CT>(ph, v, m2);
     const CT omf = BGK ? (CT)1 - rcp(ph.tau_a + clamp01(v.phi) * ph.dtau) : (CT)0;  // 1 - 1/tau_mix
@@ -1025,10 +1033,11 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
 #else
 #define PULBM_COLLIDE_ATTR
 #endif
-template <int DIMV, class S, bool BGK>
+template <int LS, class S, bool BGK>
 __global__ __launch_bounds__(256) PULBM_COLLIDE_ATTR void k_collide(CaseTab cases, const int* hdr, int step_off)
 {
-    using Mo = Model<DIMV>;
+    constexpr int DIMV = Model<LS>::DIM;
+    using Mo = Model<LS>;
     using H = typename Mo::H;
     using CT = typename Codec<S>::CT;
     using R = typename Halo1<Mo, DIMV>::R;
@@ -1037,18 +1046,19 @@ __global__ __launch_bounds__(256) PULBM_COLLIDE_ATTR void k_collide(CaseTab case
     const TileCtx t = tile_ctx<Mo>(cases, hdr, step_off);
     if (!t.active) return;
     CDesc& cs = *t.cs;
-    if (tile_at_wall<Mo>(cs, t.ox, t.oy, t.oz)) collide_tile<DIMV, S, true, BGK, R>(cs, t, sPhi, sRho, sU, sH);
-    else collide_tile<DIMV, S, false, BGK, R>(cs, t, sPhi, sRho, sU, sH);
+    if (tile_at_wall<Mo>(cs, t.ox, t.oy, t.oz)) collide_tile<LS, S, true, BGK, R>(cs, t, sPhi, sRho, sU, sH);
+    else collide_tile<LS, S, false, BGK, R>(cs, t, sPhi, sRho, sU, sH);
 }
 
 // --- initial state: equilibria of (phi0, P0, u0) in the even AA layout,
 //     previous-step pressure P[0] = P0.  Inputs are FP64 device arrays.
-template <int DIMV, class S>
+template <int LS, class S>
 __global__ __launch_bounds__(256) void k_init(CaseTab cases, const int* hdr,
                                               const double* __restrict__ phi0, const double* __restrict__ P0,
                                               const double* __restrict__ u0)
 {
-    using Mo = Model<DIMV>;
+    constexpr int DIMV = Model<LS>::DIM;
+    using Mo = Model<LS>;
     using G = typename Mo::G;
     using H = typename Mo::H;
     using CT = typename Codec<S>::CT;
@@ -1084,7 +1094,7 @@ __global__ __launch_bounds__(256) void k_init(CaseTab cases, const int* hdr,
     if (x >= cs.nx || y >= cs.ny || z >= cs.nz) return;
     const uint32_t n = (uint32_t)x + (uint32_t)cs.nx * ((uint32_t)y + (uint32_t)cs.ny * (uint32_t)z);
     NodeVals<CT> v;
-    tile_gradients<DIMV, R, CT>(sPhi, sRho, sU, lx + 1, ly + 1, lz + HR::ZH, v);
+    tile_gradients<LS, R, CT>(sPhi, sRho, sU, lx + 1, ly + 1, lz + HR::ZH, v);
     const NodeCoef<DIMV, CT> kc = node_coef<DIMV, true, CT>(ph, v, (const CT*)nullptr);
     const Slots<S> hs = slots<S>(cs.h, cs.N), gs = slots<S>(cs.g, cs.N);
     const uint32_t nb = n * (uint32_t)sizeof(S);

@@ -57,13 +57,16 @@ struct D3Q19 {
     }
 };
 
-// Hydro lattice G, phase-field lattice H and the workgroup tile of a
-// problem dimension.  Tiles are 256 threads (four 64-wide wavefronts), x
-// fastest so that a wavefront reads whole 128-byte rows of a population.
-template <int DIMV> struct Model;
+// Lattice sets: hydro lattice G, phase-field lattice H, dimension and the
+// workgroup tile.  Set 2: D2Q9 / D2Q9; set 3: D3Q27 / D3Q19; set 4: D3Q19 /
+// D3Q19 (the lattice the paper uses in 3D, Sec. II).  Tiles are 256 threads
+// (four 64-wide wavefronts), x fastest so that a wavefront reads whole
+// 128-byte rows of a population.
+template <int LS> struct Model;
 template <> struct Model<2> {
     using G = D2Q9;
     using H = D2Q9;
+    static constexpr int DIM = 2;
     static constexpr int TX = 64, TY = 4, TZ = 1;
 };
 #ifndef PULBM_TILE3
@@ -75,6 +78,15 @@ template <int X, int Y, int Z> struct Tile3 {
 template <> struct Model<3> : Tile3<PULBM_TILE3> {
     using G = D3Q27;
     using H = D3Q19;
+    static constexpr int DIM = 3;
 };
+template <> struct Model<4> : Tile3<PULBM_TILE3> {
+    using G = D3Q19;
+    using H = D3Q19;
+    static constexpr int DIM = 3;
+};
+
+// Lattice set of a case: dimension and hydro lattice size.
+__host__ __device__ constexpr int lattice_set(int dim, int q_hydro) { return dim == 2 ? 2 : (q_hydro == 19 ? 4 : 3); }
 
 }  // namespace pulbm

@@ -93,8 +93,9 @@ int validate(const pulbm_params* p)
     if (p->dim == 2 && p->nz != 1) return fail(PULBM_EINVAL, "2D cases need nz = 1");
     if (p->dim == 2 && (p->q_hydro != 9 || p->q_phase != 9))
         return fail(PULBM_EINVAL, "2D cases use D2Q9 for both lattices (q_hydro = q_phase = 9)");
-    if (p->dim == 3 && (p->q_hydro != 27 || p->q_phase != 19))
-        return fail(PULBM_EINVAL, "3D cases use D3Q27 hydro + D3Q19 phase field (27, 19)");
+    if (p->dim == 3 && ((p->q_hydro != 27 && p->q_hydro != 19) || p->q_phase != 19))
+        return fail(PULBM_EINVAL, "3D cases use a D3Q27 or D3Q19 hydro lattice and the D3Q19 phase field "
+                                  "(q_hydro 27 or 19, q_phase 19)");
     if (p->store < PULBM_STORE_FP64 || p->store > PULBM_STORE_BF16) return fail(PULBM_EINVAL, "bad store %d", p->store);
     // kernels address one field with 32-bit byte offsets (signed for the
     // periodic neighbour steps): N times the widest element must stay below 2^31
@@ -119,9 +120,9 @@ int validate(const pulbm_params* p)
     return PULBM_OK;
 }
 
-template <int DIMV> void tiles_of(const pulbm_params& p, int* ntx, int* nty, int* ntz)
+template <int LS> void tiles_of(const pulbm_params& p, int* ntx, int* nty, int* ntz)
 {
-    using Mo = Model<DIMV>;
+    using Mo = Model<LS>;
     *ntx = (p.nx + Mo::TX - 1) / Mo::TX;
     *nty = (p.ny + Mo::TY - 1) / Mo::TY;
     *ntz = (p.nz + Mo::TZ - 1) / Mo::TZ;
@@ -153,49 +154,50 @@ struct pulbm_case {
 
 namespace {
 
-template <int DIMV, class S>
+template <int LS, class S>
 void launch_step(hipStream_t st, CaseDev* const* tab, const int* hdr, int blocks, int off, int which, bool bgk)
 {
     using CT = typename Codec<S>::CT;
     const dim3 grid(blocks), block(256);
-    if (which == 0) hipLaunchKernelGGL((k_moments<DIMV, S>), grid, block, 0, st, tab, hdr, off);
-    if (which == 1) hipLaunchKernelGGL((k_pressure<DIMV, CT>), grid, block, 0, st, tab, hdr, off);
-    if (which == 2) hipLaunchKernelGGL((k_velocity<DIMV, CT>), grid, block, 0, st, tab, hdr, off);
+    if (which == 0) hipLaunchKernelGGL((k_moments<LS, S>), grid, block, 0, st, tab, hdr, off);
+    if (which == 1) hipLaunchKernelGGL((k_pressure<LS, CT>), grid, block, 0, st, tab, hdr, off);
+    if (which == 2) hipLaunchKernelGGL((k_velocity<LS, CT>), grid, block, 0, st, tab, hdr, off);
     if (which == 3) {
-        if (bgk) hipLaunchKernelGGL((k_collide<DIMV, S, true>), grid, block, 0, st, tab, hdr, off);
-        else hipLaunchKernelGGL((k_collide<DIMV, S, false>), grid, block, 0, st, tab, hdr, off);
+        if (bgk) hipLaunchKernelGGL((k_collide<LS, S, true>), grid, block, 0, st, tab, hdr, off);
+        else hipLaunchKernelGGL((k_collide<LS, S, false>), grid, block, 0, st, tab, hdr, off);
     }
 }
 
-template <int DIMV>
+template <int LS>
 void launch_dim(int store, hipStream_t st, CaseDev* const* tab, const int* hdr, int blocks, int off, int which,
                 bool bgk)
 {
     switch (store) {
-        case PULBM_STORE_FP64: launch_step<DIMV, double>(st, tab, hdr, blocks, off, which, bgk); break;
-        case PULBM_STORE_FP32: launch_step<DIMV, float>(st, tab, hdr, blocks, off, which, bgk); break;
-        case PULBM_STORE_FP16: launch_step<DIMV, _Float16>(st, tab, hdr, blocks, off, which, bgk); break;
-        default: launch_step<DIMV, uint16_t>(st, tab, hdr, blocks, off, which, bgk); break;
+        case PULBM_STORE_FP64: launch_step<LS, double>(st, tab, hdr, blocks, off, which, bgk); break;
+        case PULBM_STORE_FP32: launch_step<LS, float>(st, tab, hdr, blocks, off, which, bgk); break;
+        case PULBM_STORE_FP16: launch_step<LS, _Float16>(st, tab, hdr, blocks, off, which, bgk); break;
+        default: launch_step<LS, uint16_t>(st, tab, hdr, blocks, off, which, bgk); break;
     }
 }
 
 // which: 0 moments, 1 pressure, 2 velocity, 3 collide + stream.  blocks must
 // cover the table's tiles (rounded up to a multiple of 8); extra blocks exit.
-void launch(int dim, int store, bool bgk, hipStream_t st, CaseDev* const* tab, const int* hdr, int blocks, int off,
+void launch(int ls, int store, bool bgk, hipStream_t st, CaseDev* const* tab, const int* hdr, int blocks, int off,
             int which)
 {
-    if (dim == 2) launch_dim<2>(store, st, tab, hdr, blocks, off, which, bgk);
+    if (ls == 2) launch_dim<2>(store, st, tab, hdr, blocks, off, which, bgk);
+    else if (ls == 4) launch_dim<4>(store, st, tab, hdr, blocks, off, which, bgk);
     else launch_dim<3>(store, st, tab, hdr, blocks, off, which, bgk);
 }
 
-template <int DIMV, class S>
+template <int LS, class S>
 void launch_init_t(hipStream_t st, CaseDev* const* tab, const int* hdr, int blocks, const double* phi,
                    const double* P, const double* u)
 {
-    hipLaunchKernelGGL((k_init<DIMV, S>), dim3(blocks), dim3(256), 0, st, tab, hdr, phi, P, u);
+    hipLaunchKernelGGL((k_init<LS, S>), dim3(blocks), dim3(256), 0, st, tab, hdr, phi, P, u);
 }
 
-void launch_init(int dim, int store, hipStream_t st, CaseDev* const* tab, const int* hdr, int blocks,
+void launch_init(int ls, int store, hipStream_t st, CaseDev* const* tab, const int* hdr, int blocks,
                  const double* phi, const double* P, const double* u)
 {
 #define PULBM_INIT_CASE(D)                                                                          \
@@ -205,7 +207,7 @@ void launch_init(int dim, int store, hipStream_t st, CaseDev* const* tab, const 
         case PULBM_STORE_FP16: launch_init_t<D, _Float16>(st, tab, hdr, blocks, phi, P, u); break;  \
         default: launch_init_t<D, uint16_t>(st, tab, hdr, blocks, phi, P, u); break;                \
     }
-    if (dim == 2) { PULBM_INIT_CASE(2) } else { PULBM_INIT_CASE(3) }
+    if (ls == 2) { PULBM_INIT_CASE(2) } else if (ls == 4) { PULBM_INIT_CASE(4) } else { PULBM_INIT_CASE(3) }
 #undef PULBM_INIT_CASE
 }
 
@@ -238,7 +240,7 @@ int upload_desc(pulbm_case* c)
 int read_pass(pulbm_case* c)
 {
     for (int w = 0; w < kReadKernels; ++w)
-        launch(c->p.dim, c->p.store, c->p.collision == 1, c->stream, c->tab, c->hdr, grid_of(c->ntiles), -1, w);
+        launch(lattice_set(c->p.dim, c->p.q_hydro), c->p.store, c->p.collision == 1, c->stream, c->tab, c->hdr, grid_of(c->ntiles), -1, w);
     HIPC(hipGetLastError());
     return PULBM_OK;
 }
@@ -381,7 +383,7 @@ extern "C" int pulbm_init_fields(pulbm_case* c, const double* phi, const double*
     if (e == hipSuccess)
         e = hipMemcpyAsync(tmp + 2 * N, u, (size_t)dim * N * sizeof(double), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) {
-        launch_init(dim, c->p.store, c->stream, c->tab, c->hdr, grid_of(c->ntiles), tmp, tmp + N, tmp + 2 * N);
+        launch_init(lattice_set(dim, c->p.q_hydro), c->p.store, c->stream, c->tab, c->hdr, grid_of(c->ntiles), tmp, tmp + N, tmp + 2 * N);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -399,7 +401,7 @@ static void queue_direct(pulbm_case* c, int count)
 {
     for (int k = 0; k < count; ++k)
         for (int w = 0; w < kStepKernels; ++w)
-            launch(c->p.dim, c->p.store, c->p.collision == 1, c->stream, c->tab, c->hdr, grid_of(c->ntiles), k, w);
+            launch(lattice_set(c->p.dim, c->p.q_hydro), c->p.store, c->p.collision == 1, c->stream, c->tab, c->hdr, grid_of(c->ntiles), k, w);
     hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, c->stream, c->tab, c->hdr, count);
 }
 
@@ -435,7 +437,7 @@ extern "C" int pulbm_step_timed(pulbm_case* c, int64_t nsteps, double* ms)
     for (int64_t s = 0; s < nsteps && rc == PULBM_OK; ++s) {
         (void)hipEventRecord(ev[0], c->stream);
         for (int w = 0; w < kStepKernels; ++w) {
-            launch(c->p.dim, c->p.store, c->p.collision == 1, c->stream, c->tab, c->hdr, grid_of(c->ntiles), 0, w);
+            launch(lattice_set(c->p.dim, c->p.q_hydro), c->p.store, c->p.collision == 1, c->stream, c->tab, c->hdr, grid_of(c->ntiles), 0, w);
             (void)hipEventRecord(ev[w + 1], c->stream);
         }
         hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, c->stream, c->tab, c->hdr, 1);
@@ -634,7 +636,7 @@ struct pulbm_batch {
         int which = 0;
         int cap = 0, ncases = 0, tiles = 0, grid = 0;
         std::map<int, hipGraphExec_t> graphs;  // by ksteps, captured for `grid` blocks
-    } tab[4];  // index (dim - 2) + 2 * collision
+    } tab[6];  // index (lattice set - 2) + 3 * collision
     bool dirty = true;
 };
 
@@ -720,8 +722,8 @@ void drop_graphs(pulbm_batch* b, pulbm_batch::Tab& t)
 
 int rebuild_tables(pulbm_batch* b)
 {
-    for (int di = 0; di < 4; ++di) {
-        const int dim = (di & 1) + 2, coll = di >> 1;
+    for (int di = 0; di < 6; ++di) {
+        const int ls = di % 3 + 2, coll = di / 3;
         pulbm_batch::Tab& t = b->tab[di];
         if (t.cap == 0) {  // sized once for every slot
             t.cap = b->max_slots;
@@ -740,7 +742,7 @@ int rebuild_tables(pulbm_batch* b)
         int n = 0;
         hdr[2] = 0;
         for (auto& s : b->slots)
-            if (s.c && s.c->p.dim == dim && s.c->p.collision == coll) {
+            if (s.c && lattice_set(s.c->p.dim, s.c->p.q_hydro) == ls && s.c->p.collision == coll) {
                 ptr[n] = s.c->d;
                 hdr[3 + n] = hdr[2 + n] + s.c->ntiles;
                 ++n;
@@ -857,7 +859,7 @@ extern "C" int pulbm_batch_advance(pulbm_batch* b, int32_t ksteps)
     int rc = sync_advances(b, 0);
     if (rc) return rc;
     if (b->dirty && (rc = rebuild_tables(b))) return rc;
-    for (int di = 0; di < 4; ++di) {
+    for (int di = 0; di < 6; ++di) {
         pulbm_batch::Tab& t = b->tab[di];
         if (t.ncases == 0) continue;
         auto it = t.graphs.find(ksteps);
@@ -867,7 +869,7 @@ extern "C" int pulbm_batch_advance(pulbm_batch* b, int32_t ksteps)
             HIPC(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
             for (int k = 0; k < ksteps; ++k)
                 for (int w = 0; w < kStepKernels; ++w)
-                    launch((di & 1) + 2, b->store, (di >> 1) == 1, b->stream, t.dtab, t.dhdr, t.grid, k, w);
+                    launch(di % 3 + 2, b->store, di / 3 == 1, b->stream, t.dtab, t.dhdr, t.grid, k, w);
             hipLaunchKernelGGL(k_advance, dim3((t.cap + 63) / 64), dim3(64), 0, b->stream, t.dtab, t.dhdr, ksteps);
             HIPC(hipStreamEndCapture(b->stream, &g));
             HIPC(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));

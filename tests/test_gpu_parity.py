@@ -236,3 +236,28 @@ def test_bgk_collision_matches_oracle(case, store, tol):
         g.step(s)
         o.step(s)
         _compare(g.read_fields(), o.read_fields(), tol, f"{case} bgk {store} +{s}")
+
+
+@pytest.mark.parametrize("store,tol", [("fp64", TOL64), ("fp32", 2e-5)])
+@pytest.mark.parametrize("collision", ["filter", "bgk"])
+@pytest.mark.parametrize("case", ["3d_periodic_ragged", "3d_walls_z_gravity", "3d_all_walls"])
+def test_d3q19_hydro_matches_oracle(case, collision, store, tol):
+    """D3Q19 for the hydrodynamic populations as well as the phase field
+    (the lattice of the paper's 3D runs, Sec. II)."""
+    kw = dict(CASES[case])
+    dim, nx, ny = kw.pop("dim"), kw.pop("nx"), kw.pop("ny")
+    nz = kw.pop("nz", 1)
+    nu = (0.05, 0.15) if collision == "filter" else (0.1, 0.1)
+    cfg = W.base_case(dim, nx, ny, nz, q_hydro=19, nu_heavy=nu[0], nu_light=nu[1], sigma=0.01,
+                      store=store, collision=collision, **kw)
+    f = _fields(cfg)
+    g = B.Case(cfg)
+    g.init_fields(*f)
+    o = oracle.OracleCase(dict(cfg, store="fp64"))
+    o.init_fields(*f)
+    _compare(g.read_fields(), o.read_fields(), tol, f"{case} d3q19 {collision} {store} step 0")
+    for s in (1, 6, 23):
+        g.step(s)
+        o.step(s)
+        _compare(g.read_fields(), o.read_fields(), tol, f"{case} d3q19 {collision} {store} +{s}")
+    assert g.diagnostics()["nonfinite"] == 0

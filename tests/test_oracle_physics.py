@@ -107,6 +107,27 @@ def test_shear_wave_decay(phase, nu, collision):
     assert abs(rate - nu * kk * kk) < 0.01 * nu * kk * kk
 
 
+@pytest.mark.parametrize("q_hydro", [27, 19])
+def test_shear_wave_decay_3d(q_hydro):
+    """Decay rate nu k^2 of a 3D shear wave on either hydrodynamic lattice
+    (D3Q27, or D3Q19 as in the paper's 3D runs), heavy phase, nu = 0.05."""
+    ny, nu = 32, 0.05
+    cfg = W.base_case(3, 4, ny, 4, nu_heavy=nu, nu_light=nu, q_hydro=q_hydro)
+    oc = oracle.OracleCase(cfg)
+    oc.init_fields(*W.shear_wave(cfg, amp=1e-4, heavy=True))
+    s = np.sin(2 * math.pi * np.arange(ny) / ny)
+    amps, ts = [], []
+    oc.step(50)
+    for k in range(5):
+        _, _, u = oc.read_fields()
+        amps.append((u[0, :, :, :].mean(axis=(0, 2)) * s).sum() / (s * s).sum())
+        ts.append(50 + 100 * k)
+        oc.step(100)
+    rate = -np.polyfit(ts, np.log(amps), 1)[0]
+    kk = 2 * math.pi / ny
+    assert abs(rate - nu * kk * kk) < 0.01 * nu * kk * kk
+
+
 def test_filter_collision_is_more_robust_than_bgk():
     """Sec. II adopts the filter collision for robustness: at density ratio
     1000 and nu = 0.03 the BGK collision diverges within 2000 steps on a
