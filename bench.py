@@ -18,6 +18,9 @@ Printed as one JSON line:
   fp16_store     the same workload with FP16 storage
   d3q19_hydro    the same workload on D3Q19 for the hydrodynamic populations
                  too (the lattice of the paper's 3D runs), FP32 and FP16
+  workloads      throughput at the real sizes of the 3D rising bubble (256^3,
+                 walls in z; FP32, FP16 and BF16 storage) and the dam break
+                 (512 x 256 x 256, walls on all faces; FP16 and FP32)
   serving        a seeded Poisson stream of droplet / bubble requests served
                  by continuous batching, p50 / p99 latency and aggregate MLUPS,
                  beside the same stream run one case at a time
@@ -193,6 +196,39 @@ def table1_leg(t_end=1.0, samples=4):
     return out
 
 
+def workloads_leg(steps=100, warmup=10):
+    """MLUPS, effective HBM GB/s (state bytes per node update x MLUPS) and the
+    collide kernel's GB/s (algorithmic bytes / HIP-event time) of the large
+    workloads at their real sizes."""
+    import gc
+
+    from paper_2512_01027_amd import workloads as W
+
+    runs = [("rising_bubble_256cube", lambda st: W.config_rising_bubble_3d(256, store=st), ("fp32", "fp16", "bf16")),
+            ("dam_break_512x256x256", lambda st: W.config_dam_break_3d(store=st), ("fp16", "fp32"))]
+    out = {}
+    for name, make, stores in runs:
+        leg = {}
+        cfg, fields, _ = make(stores[0])
+        n = cfg["nx"] * cfg["ny"] * cfg["nz"]
+        for st in stores:
+            sb = {"fp32": 4, "fp16": 2, "bf16": 2}[st]
+            dt, ms, dg = run_gpu(dict(cfg, store=st), fields, steps, warmup)
+            m = n * steps / dt / 1e6
+            eff = m * 1e6 * state_bytes(sb) / 1e9
+            leg[st] = {"MLUPS": round(m, 1), "effective_GBs": round(eff, 1),
+                       "effective_frac_of_peak": round(eff / HBM_PEAK_GBS, 4),
+                       "collide_GBs": round(kernel_bytes(sb)["collide"] * n / (ms[3] * 1e-3) / 1e9, 1),
+                       "kernel_ms": {k: round(float(v), 4) for k, v in zip(KERNELS, ms)},
+                       "nonfinite": dg["nonfinite"]}
+        leg["nodes"] = n
+        leg["steps"] = steps
+        out[name] = leg
+        del fields
+        gc.collect()
+    return out
+
+
 def cpu_baseline(cfg, fields):
     import oracle
 
@@ -221,6 +257,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-table1", action="store_true")
     ap.add_argument("--no-d3q19", action="store_true")
+    ap.add_argument("--no-workloads", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -258,9 +295,9 @@ def main():
         "config": {"workload": f"3D {args.n}^3 periodic droplet R={24 * args.n // 128} translated with "
                                "u=(0.05,0.02,0), rho ratio 1000, D3Q27 hydro + D3Q19 phase field, "
                                "FP32 store and compute", "nodes": N, "store": "fp32"},
-        "roofline": {"bound": "hbm", "kernel": "k_collide<3, float>", "achieved": round(ach, 1),
+        "roofline": {"bound": "hbm", "kernel": "k_collide<3, float, false>", "achieved": round(ach, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                     "traffic": traffic_of("pulbm::k_collide<3, float>", args.n),
+                     "traffic": traffic_of("pulbm::k_collide<3, float, false>", args.n),
                      "algorithmic_bytes_per_launch": kb["collide"] * N},
         "hbm": {"state_bytes_per_node_update": state_bytes(4), "effective_GBs": round(eff, 1),
                 "frac_of_peak": round(eff / HBM_PEAK_GBS, 4), "device_copy_GBs": copy_gbs,
@@ -292,6 +329,8 @@ def main():
                           "effective_GBs": round(m19 * 1e6 * state_bytes(sb, pops=38) / 1e9, 1),
                           "nonfinite": dg19["nonfinite"]}
         out["d3q19_hydro"] = leg
+    if not args.no_workloads:
+        out["workloads"] = workloads_leg()
     if not args.no_table1:
         out["table1_rising_bubble"] = table1_leg()
     if not args.no_cpu:

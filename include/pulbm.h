@@ -47,9 +47,10 @@ extern "C" {
 #define PULBM_STORE_FP64 0 /* FP64 (FP64)                                             */
 #define PULBM_STORE_FP32 1 /* FP32 (FP32; pressure reconstruction and sums in FP64)   */
 #define PULBM_STORE_FP16 2 /* FP16 shifted and scaled populations (FP32 compute):   */
-                           /* h_j - w_j phi (phi of the reading node, previous     */
-                           /* step) and g_i (already small: its pressure part is   */
-                           /* kept apart), scaled by powers of two                 */
+                           /* h_j - w_j phi and g_i - w_i c_i.u / T, with phi and  */
+                           /* u of the reading node at the previous step (the     */
+                           /* pressure part of g is kept apart), scaled by powers */
+                           /* of two                                               */
 #define PULBM_STORE_BF16 3 /* BF16, the same shifted populations (FP32 compute)     */
 
 /* Case parameters, lattice units (Sec. II; defaults of Sec. III in brackets). */
@@ -112,7 +113,7 @@ int pulbm_read_fields(pulbm_case* c, double* phi, double* P, double* u);
 int pulbm_diagnostics(pulbm_case* c, pulbm_diag* d);
 
 /* Restart image (distributions in their storage precision, previous-step
- * pressure and phi, step count, parameters).  checkpoint_bytes gives the
+ * pressure, phi and u, step count, parameters).  checkpoint_bytes gives the
  * size. */
 int pulbm_checkpoint_bytes(const pulbm_case* c, size_t* bytes);
 int pulbm_checkpoint(pulbm_case* c, void* host_buf, size_t bytes);

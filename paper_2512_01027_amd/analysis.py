@@ -1,4 +1,5 @@
-"""Diagnostics of a rising bubble (Sec. III.D) from the fields read back.
+"""Diagnostics of a rising bubble (Sec. III.D) and of a head-on droplet
+collision (Sec. III) from the fields read back.
 
 The bubble is the light fluid (phi < 1/2).  With its indicator weight
 b = 1 - clamp(phi, 0, 1):
@@ -8,6 +9,12 @@ b = 1 - clamp(phi, 0, 1):
                    the perimeter of the phi = 1/2 contour (1 for a circle,
                    below 1 as the bubble deforms), with the contour traced by
                    marching squares on the node values.
+Head-on collision (heavy fluid, phi >= 1/2, is water):
+    droplets       connected pieces of phi >= 1/2 (faces connect; periodic
+                   wrap joins pieces across the box edges)
+    extent         largest distance of a water node from the collision axis
+                   (the disc radius) and the water's length along the axis
+    air speed      largest |u| where phi < 0.1, against the approach speed
 Host-side numpy on arrays already copied back; not part of the time step.
 """
 from __future__ import annotations
@@ -76,3 +83,53 @@ def circularity(phi2d):
     """Circle perimeter of the bubble's area over its contour length (2D)."""
     area = float(_weights(phi2d).sum())
     return 2.0 * math.sqrt(math.pi * area) / _contour_length(phi2d)
+
+
+def droplet_count(phi, level=0.5):
+    """Number of connected water pieces (phi >= level) of a periodic 3D box,
+    6-neighbour connectivity."""
+    from scipy import ndimage
+
+    lab, n = ndimage.label(phi >= level)
+    if n == 0:
+        return 0
+    parent = list(range(n + 1))
+
+    def root(a):
+        while parent[a] != a:
+            parent[a] = parent[parent[a]]
+            a = parent[a]
+        return a
+
+    for ax in range(phi.ndim):
+        lo = np.take(lab, 0, axis=ax)
+        hi = np.take(lab, -1, axis=ax)
+        for a, b in zip(lo[(lo > 0) & (hi > 0)], hi[(lo > 0) & (hi > 0)]):
+            ra, rb = root(int(a)), root(int(b))
+            if ra != rb:
+                parent[ra] = rb
+    return len({root(k) for k in range(1, n + 1)})
+
+
+def collision_extent(phi, axis_yz=None, level=0.5):
+    """(disc radius, length along x) of the water, phi indexed [z, y, x],
+    collision axis along x through (y, z) = axis_yz (default: box centre)."""
+    nz, ny, nx = phi.shape
+    if axis_yz is None:
+        axis_yz = (ny / 2.0, nz / 2.0)
+    w = phi >= level
+    if not w.any():
+        return 0.0, 0.0
+    z, y, x = np.nonzero(w)
+    r = np.sqrt((y - axis_yz[0]) ** 2 + (z - axis_yz[1]) ** 2)
+    return float(r.max()), float(x.max() - x.min() + 1)
+
+
+def max_air_speed(phi, u, level=0.1):
+    """Largest |u| over the air nodes (phi < level)."""
+    air = phi < level
+    if not air.any():
+        return 0.0
+    sp = np.sqrt((u ** 2).sum(axis=0))
+    return float(sp[air].max())
+

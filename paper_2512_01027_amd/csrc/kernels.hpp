@@ -61,7 +61,8 @@ struct CaseDev {
                        //        streamed populations carry (the rest population holds
                        //        g_0 - P/(rho_ref T), so the previous P is added back)
     void* M2;          // 3 (2D) or 6 (3D) * N scratch: sum g c c
-    void* U;           // dim*N  velocity u of the current step
+    void* U[2];        // dim*N each: velocity of this step at U[step & 1]; U[(step + 1) & 1]
+                       // keeps the previous step's, the second reference of the 2-byte codecs
     double rho_a, rho_w, tau_a, tau_w, tau_phi, M, W, sigma, lambda_b;
     double grav[3];
     double h_scale, h_inv_scale, g_scale, g_inv_scale;
@@ -617,6 +618,48 @@ __device__ __forceinline__ CT h_reference(void* phi_prev, uint32_t n)
     else return (CT)0;
 }
 
+// Shifts of the 2-byte codecs: a population is stored less the part of its
+// equilibrium that the node reading it rebuilds from its own values of the
+// step before: w_j phi for h, w_i c_i.u / T for g (T = 1/3).  Writer and
+// reader evaluate one expression on the same FP32 values, so the reader's
+// decode of a value equals the writer's own decode of it.
+template <class L, int D, class CT>
+__device__ __forceinline__ CT c_dot(int j, const CT* u)
+{
+    CT cu = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        if (L::c(j, a) == 1) cu += u[a];
+        if (L::c(j, a) == -1) cu -= u[a];
+    }
+    return cu;
+}
+template <class CT> __device__ __forceinline__ CT g_shift(CT w, CT cu) { return (w * (CT)3) * cu; }
+#ifdef PULBM_SHIFT_FACE_EDGE
+template <class L> constexpr bool shifted_dir(int i) { return (L::c(i, 0) != 0) + (L::c(i, 1) != 0) + (L::c(i, 2) != 0) < 3; }
+#else
+template <class L> constexpr bool shifted_dir(int) { return true; }
+#endif
+// shift of an incoming g_i read by a node whose previous-step velocity is u
+template <class G, int D, class CT>
+__device__ __forceinline__ CT g_ref(int i, const CT* u)
+{
+    return shifted_dir<G>(i) ? g_shift((CT)G::w(i), c_dot<G, D>(i, u)) : (CT)0;
+}
+
+// previous-step velocity of node n in 2-byte storage (wider storage: zero, unread)
+template <class S, int D, class CT = typename Codec<S>::CT>
+__device__ __forceinline__ void u_reference(void* u_prev, int64_t N, uint32_t n, CT* ur)
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) ur[a] = 0;
+    if constexpr (sizeof(S) == 2) {
+        const Slots<CT> Up = slots<CT>(u_prev, N);
+#pragma unroll
+        for (int a = 0; a < D; ++a) ur[a] = *Up.at(a, n * (uint32_t)sizeof(CT));
+    }
+}
+
 // --- moments: phi, u* = sum g c, P*, M2 (per node; no halo)
 template <int LS, class S, bool WALL>
 __device__ __forceinline__ void moments_node(CDesc& cs, int x, int y, int z, bool odd)
@@ -631,8 +674,11 @@ __device__ __forceinline__ void moments_node(CDesc& cs, int x, int y, int z, boo
     const Nav nv = make_nav(cs, x, y, z, (int)sizeof(S));
     const Slots<S> hs = slots<S>(cs.h, cs.N), gs = slots<S>(cs.g, cs.N);
     const CT hsc = (CT)cs.h_inv_scale, gsc = (CT)cs.g_inv_scale;
-    // 2-byte storage holds h_j - w_j phi, phi of this node one step earlier
+    // 2-byte storage holds the populations less shifts made of phi (h) and
+    // u (g) of this node one step earlier
     const CT php = h_reference<S>(cs.phi[odd ? 0 : 1], n);
+    CT ur[3];
+    u_reference<S, DIMV>(cs.U[odd ? 0 : 1], cs.N, n, ur);
     CT phi = 0;
 #pragma unroll
     for (int j = 0; j < H::Q; ++j)
@@ -641,7 +687,8 @@ __device__ __forceinline__ void moments_node(CDesc& cs, int x, int y, int z, boo
     CT sum = 0, J[3] = {0, 0, 0}, m2[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
     for (int i = 0; i < G::Q; ++i) {
-        const CT f = Codec<S>::dec(aa_load<G, WALL, nt_access<S, kLoadMoments>()>(gs, nb, nv, i, odd), gsc, (CT)0);
+        const CT f = Codec<S>::dec(aa_load<G, WALL, nt_access<S, kLoadMoments>()>(gs, nb, nv, i, odd), gsc,
+                                   g_ref<G, DIMV>(i, ur));
         sum += f;
 #pragma unroll
         for (int a = 0; a < DIMV; ++a) {
@@ -680,7 +727,6 @@ __device__ __forceinline__ void moments_node(CDesc& cs, int x, int y, int z, boo
 template <int LS, class S>
 __global__ __launch_bounds__(256) void k_moments(CaseTab cases, const int* hdr, int step_off)
 {
-    constexpr int DIMV = Model<LS>::DIM;
     using Mo = Model<LS>;
     const TileCtx t = tile_ctx<Mo>(cases, hdr, step_off);
     if (!t.active) return;
@@ -814,7 +860,7 @@ __device__ __forceinline__ void velocity_tile(CDesc& cs, const TileCtx& t, CT* s
             if (G::c(i, a) == -1) gr[a] -= d;
         }
     }
-    const Slots<CT> Js = slots<CT>(cs.J, cs.N), Us = slots<CT>(cs.U, cs.N);
+    const Slots<CT> Js = slots<CT>(cs.J, cs.N), Us = slots<CT>(cs.U[t.step & 1], cs.N);
     const uint32_t na = n * (uint32_t)sizeof(CT);
 #pragma unroll
     for (int a = 0; a < DIMV; ++a) *Us.at(a, na) = *Js.at(a, na) - gr[a] * (CT)3.0 * irho;
@@ -894,8 +940,10 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
     CT m2[NM];
     CT php = 0;  // reference of the incoming h (2-byte storage)
     CT dP = 0;   // BGK: (previous P - new P) / (rho_ref T), restores the stored rest population
+    CT ur[3] = {0, 0, 0};  // BGK, 2-byte storage: reference of the incoming g
     if (inside) {
         php = h_reference<S>(cs.phi[(t.step + 1) & 1], n);
+        if constexpr (BGK) u_reference<S, DIMV>(cs.U[(t.step + 1) & 1], cs.N, n, ur);
 #pragma unroll
         for (int j = 0; j < H::Q; ++j) hraw[j] = aa_load<H, WALL, nt_access<S, kLoadCollide>()>(hs, nb, nv, j, odd);
         if constexpr (BGK) {
@@ -908,7 +956,7 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
         }
     }
     // halo of phi, rho and u
-    const Slots<CT> Us = slots<CT>(cs.U, cs.N);
+    const Slots<CT> Us = slots<CT>(cs.U[t.step & 1], cs.N);
     // fixed trip count, fully unrolled: every halo load is issued before the
     // first LDS write waits on one
 #pragma unroll
@@ -940,16 +988,32 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
     const CT omf = BGK ? (CT)1 - rcp(ph.tau_a + clamp01(v.phi) * ph.dtau) : (CT)0;  // 1 - 1/tau_mix
     const CT hisc = (CT)cs.h_inv_scale, hsc = (CT)cs.h_scale, gsc = (CT)cs.g_scale, gsc_in = (CT)cs.g_inv_scale;
     const CT corr = (CT)6.0 * rcp(kc.rho);  // 2 / (rho T)
-    // reference of an outgoing h_j in 2-byte storage: w_j phi (this step) of
-    // the node that reads it next step -- x + c_j, or x itself for a
-    // population reflected at a wall
+    // shifts of an outgoing g_i and h_i in 2-byte storage, from phi and u
+    // (this step) of the node that reads it next step: x + c_i, or x itself
+    // for a population reflected at a wall, which that node reads as moving
+    // along -c_i
     const int cx = lx + 1, cy = ly + 1, cz = lz + HR::ZH, c0 = R::idx(cx, cy, cz);
-    auto href = [&](int j, bool reflected) -> CT {
+    // (each taken where it is used, which keeps the register budget)
+    auto gref_out = [&](int i, bool reflected) -> CT {
         if constexpr (sizeof(S) != 2) {
             return (CT)0;
         } else {
-            const int k = reflected ? c0 : R::idx(cx + H::c(j, 0), cy + H::c(j, 1), cz + H::c(j, 2));
-            return (CT)H::w(j) * sPhi[k];
+            const int k = reflected ? c0 : R::idx(cx + G::c(i, 0), cy + G::c(i, 1), cz + G::c(i, 2));
+            CT ud[3] = {0, 0, 0};
+#pragma unroll
+            for (int a = 0; a < DIMV; ++a)
+                if (G::c(i, a) != 0 && shifted_dir<G>(i)) ud[a] = sU[a][k];
+            CT cu = c_dot<G, DIMV>(i, ud);
+            if (reflected) cu = -cu;
+            return shifted_dir<G>(i) ? g_shift((CT)G::w(i), cu) : (CT)0;
+        }
+    };
+    auto href_out = [&](int i, bool reflected) -> CT {
+        if constexpr (sizeof(S) != 2) {
+            return (CT)0;
+        } else {
+            const int k = reflected ? c0 : R::idx(cx + H::c(i, 0), cy + H::c(i, 1), cz + H::c(i, 2));
+            return (CT)H::w(i) * sPhi[k];
         }
     };
     // rest direction of g, the opposite pairs, then the rest direction of h;
@@ -960,7 +1024,8 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
         if constexpr (BGK) {
             // BGK (Eq. BGK_LBeq_hydroeq) on the full rest population; both the
             // stored incoming value and the equilibrium lack their P / (rho_ref T)
-            const CT gin = Codec<S>::dec(aa_load<G, WALL, false>(gs, nb, nv, 0, odd), gsc_in, (CT)0) + dP;
+            const CT gin = Codec<S>::dec(aa_load<G, WALL, false>(gs, nb, nv, 0, odd), gsc_in,
+                                         g_ref<G, DIMV>(0, ur)) + dP;
             g0 += omf * (gin - g0);
         }
         aa_store<G, WALL, nt_access<S, kStoreCollide>()>(gs, nb, nv, 0, odd, Codec<S>::enc(g0, gsc, (CT)0), false);
@@ -977,8 +1042,10 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
         if constexpr (BGK) {
             // incoming g_i, g_i+1: within a step a node reads and writes one set
             // of slots (AA), and the slots of this pair are written just below
-            const CT ai = Codec<S>::dec(aa_load<G, WALL, false>(gs, nb, nv, i, odd), gsc_in, (CT)0);
-            const CT ak = Codec<S>::dec(aa_load<G, WALL, false>(gs, nb, nv, i + 1, odd), gsc_in, (CT)0);
+            const CT ai = Codec<S>::dec(aa_load<G, WALL, false>(gs, nb, nv, i, odd), gsc_in,
+                                        g_ref<G, DIMV>(i, ur));
+            const CT ak = Codec<S>::dec(aa_load<G, WALL, false>(gs, nb, nv, i + 1, odd), gsc_in,
+                                        g_ref<G, DIMV>(i + 1, ur));
             gi += omf * (ai - gi);
             gk += omf * (ak - gk);
         }
@@ -994,14 +1061,16 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
             gi -= bi ? fc : (CT)0;
             gk += bk ? fc : (CT)0;
         }
-        aa_store<G, WALL, nt_access<S, kStoreCollide>()>(gs, nb, nv, i, odd, Codec<S>::enc(gi, gsc, (CT)0), bi);
-        aa_store<G, WALL, nt_access<S, kStoreCollide>()>(gs, nb, nv, i + 1, odd, Codec<S>::enc(gk, gsc, (CT)0), bk);
+        aa_store<G, WALL, nt_access<S, kStoreCollide>()>(gs, nb, nv, i, odd, Codec<S>::enc(gi, gsc, gref_out(i, bi)),
+                                                         bi);
+        aa_store<G, WALL, nt_access<S, kStoreCollide>()>(gs, nb, nv, i + 1, odd,
+                                                         Codec<S>::enc(gk, gsc, gref_out(i + 1, bk)), bk);
         if (i < H::Q) {
             const CT hi = Codec<S>::dec(sH[i][threadIdx.x], hisc, php * (CT)H::w(i));
             const CT hk = Codec<S>::dec(sH[i + 1][threadIdx.x], hisc, php * (CT)H::w(i + 1));
             CT oi, ok;
             h_pair<H, DIMV, false>(ph, v, kc, i, hi, hk, &oi, &ok);
-            const CT ri = href(i, bi), rk = href(i + 1, bk);
+            const CT ri = href_out(i, bi), rk = href_out(i + 1, bk);
             const S ei = Codec<S>::enc(oi, hsc, ri), ek = Codec<S>::enc(ok, hsc, rk);
             hmoved += (hi - Codec<S>::dec(ei, hisc, ri)) + (hk - Codec<S>::dec(ek, hisc, rk));
             aa_store<H, WALL, nt_access<S, kStoreCollide>()>(hs, nb, nv, i, odd, ei, bi);
@@ -1016,7 +1085,7 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
     {
         const CT h0 = Codec<S>::dec(sH[0][threadIdx.x], hisc, php * (CT)H::w(0));
         aa_store<H, WALL, nt_access<S, kStoreCollide>()>(hs, nb, nv, 0, odd,
-                                                         Codec<S>::enc(h0 + hmoved, hsc, href(0, true)), false);
+                                                         Codec<S>::enc(h0 + hmoved, hsc, href_out(0, true)), false);
     }
 }
 
@@ -1110,10 +1179,16 @@ __global__ __launch_bounds__(256) void k_init(CaseTab cases, const int* hdr,
     }
     // rest population as the remainder, so that sum_j h_j = phi0 exactly
     *hs.at(0, nb) = Codec<S>::enc(v.phi - hmoved, hsc, phr * (CT)H::w(0));
+    // 2-byte storage: g_i - w_i c_i.u0 / T (the previous-step u of step 0 is u0)
 #pragma unroll
-    for (int i = 0; i < G::Q; ++i) *gs.at(i, nb) = Codec<S>::enc(g_out<G, DIMV, true>(v, kc, i), gsc, (CT)0);
+    for (int i = 0; i < G::Q; ++i)
+        *gs.at(i, nb) = Codec<S>::enc(g_out<G, DIMV, true>(v, kc, i), gsc,
+                                      sizeof(S) == 2 ? g_ref<G, DIMV>(i, v.u) : (CT)0);
     *at_node<CT>(cs.P[0], n) = (CT)P0[n];
     *at_node<CT>(cs.phi[1], n) = v.phi;
+    const Slots<CT> U1 = slots<CT>(cs.U[1], cs.N);
+#pragma unroll
+    for (int a = 0; a < DIMV; ++a) *U1.at(a, n * (uint32_t)sizeof(CT)) = v.u[a];
 }
 
 // --- step counters: every case of a table advances by k (up to its end).
@@ -1151,7 +1226,7 @@ __global__ __launch_bounds__(256) void k_diag(const CaseDev* __restrict__ csp, d
     const int64_t N = cs.N;
     const AT* phi = (const AT*)cs.phi[cs.step & 1];
     const AT* P = (const AT*)cs.P[(cs.step + 1) & 1];
-    const AT* U = (const AT*)cs.U;
+    const AT* U = (const AT*)cs.U[cs.step & 1];
     double acc[kDiagVals] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < N; n += (int64_t)gridDim.x * 256) {
         const double f = (double)phi[n];

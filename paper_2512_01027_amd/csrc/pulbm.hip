@@ -56,7 +56,7 @@ int store_bytes(int store) { return store == PULBM_STORE_FP64 ? 8 : store == PUL
 int aux_bytes(int store) { return store == PULBM_STORE_FP64 ? 8 : 4; }
 
 struct Layout {
-    size_t h, g, P0, P1, phi0, phi1, J, Ps, M2, U, desc, tab, partial, diag, total;
+    size_t h, g, P0, P1, phi0, phi1, J, Ps, M2, U0, U1, desc, tab, partial, diag, total;
 };
 
 Layout make_layout(const pulbm_params& p)
@@ -76,7 +76,8 @@ Layout make_layout(const pulbm_params& p)
     L.J = put((size_t)dim * N * ab);
     L.Ps = put(N * ab);
     L.M2 = put((size_t)nm * N * ab);
-    L.U = put((size_t)dim * N * ab);
+    L.U0 = put((size_t)dim * N * ab);
+    L.U1 = put((size_t)dim * N * ab);
     L.desc = put(sizeof(CaseDev));
     L.tab = put(sizeof(CaseDev*) + 4 * sizeof(int));
     L.partial = put((size_t)kDiagBlocks * kDiagVals * sizeof(double));
@@ -324,7 +325,7 @@ extern "C" int pulbm_create(const pulbm_params* p, void* dev_arena, size_t arena
     h.P[0] = c->base + L.P0; h.P[1] = c->base + L.P1;
     h.phi[0] = c->base + L.phi0; h.phi[1] = c->base + L.phi1;
     h.J = c->base + L.J; h.Ps = c->base + L.Ps;
-    h.M2 = c->base + L.M2; h.U = c->base + L.U;
+    h.M2 = c->base + L.M2; h.U[0] = c->base + L.U0; h.U[1] = c->base + L.U1;
     h.rho_a = p->rho_light; h.rho_w = p->rho_heavy;
     h.tau_a = p->nu_light / kT + 0.5;
     h.tau_w = p->nu_heavy / kT + 0.5;
@@ -369,12 +370,13 @@ extern "C" int pulbm_init_fields(pulbm_case* c, const double* phi, const double*
     c->h.step_end = INT64_MAX;
     int rc = upload_desc(c);
     if (rc) return rc;
-    // stage the FP64 inputs in the case's own scratch fields (u*, S, M2, u),
-    // which k_init does not touch; no allocation on this path
+    // stage the FP64 inputs in the case's own scratch fields (u*, P*, M2,
+    // U[0]), which k_init does not touch (it writes U[1]); no allocation on
+    // this path
     const size_t bytes = (2 + (size_t)dim) * N * sizeof(double);
     double* tmp = (double*)(c->base + c->L.J);
     bool own_tmp = false;
-    if (bytes > c->L.desc - c->L.J) {
+    if (bytes > c->L.U1 - c->L.J) {
         HIPC(hipMalloc((void**)&tmp, bytes));
         own_tmp = true;
     }
@@ -469,7 +471,7 @@ extern "C" int pulbm_read_fields(pulbm_case* c, double* phi, double* P, double* 
     const size_t N = (size_t)c->h.N;
     if ((rc = fetch(c, c->h.phi[c->step & 1], phi, N))) return rc;
     if ((rc = fetch(c, c->h.P[(c->step + 1) & 1], P, N))) return rc;
-    if ((rc = fetch(c, c->h.U, u, (size_t)c->p.dim * N))) return rc;
+    if ((rc = fetch(c, c->h.U[c->step & 1], u, (size_t)c->p.dim * N))) return rc;
     return PULBM_OK;
 }
 
@@ -500,10 +502,11 @@ extern "C" int pulbm_diagnostics(pulbm_case* c, pulbm_diag* d)
     return PULBM_OK;
 }
 
-// Restart image: header, h, g, previous-step pressure, previous-step phi (the
-// reference of the 2-byte h codec).
+// Restart image: header, h, g, previous-step pressure, previous-step phi and
+// u (the references of the 2-byte codecs).
 namespace {
-constexpr char kCkptMagic[9] = "PULBMCK2";
+constexpr char kCkptMagic[9] = "PULBMCK3";
+constexpr int32_t kCkptVersion = 3;
 struct CkptHeader {
     char magic[8];
     int32_t version, store;
@@ -517,7 +520,7 @@ extern "C" int pulbm_checkpoint_bytes(const pulbm_case* c, size_t* bytes)
 {
     if (!c || !bytes) return fail(PULBM_EINVAL, "NULL argument");
     const size_t N = (size_t)c->h.N, sb = store_bytes(c->p.store), ab = aux_bytes(c->p.store);
-    *bytes = sizeof(CkptHeader) + (size_t)(c->p.q_phase + c->p.q_hydro) * N * sb + 2 * N * ab;
+    *bytes = sizeof(CkptHeader) + (size_t)(c->p.q_phase + c->p.q_hydro) * N * sb + (2 + (size_t)c->p.dim) * N * ab;
     return PULBM_OK;
 }
 
@@ -532,7 +535,7 @@ extern "C" int pulbm_checkpoint(pulbm_case* c, void* buf, size_t bytes)
     CkptHeader hd;
     std::memset(&hd, 0, sizeof hd);
     std::memcpy(hd.magic, kCkptMagic, 8);
-    hd.version = 2;
+    hd.version = kCkptVersion;
     hd.store = c->p.store;
     hd.p = c->p;
     hd.step = c->step;
@@ -549,6 +552,9 @@ extern "C" int pulbm_checkpoint(pulbm_case* c, void* buf, size_t bytes)
     HIPC(hipMemcpyAsync(o, c->h.P[c->step & 1], hd.P_bytes, hipMemcpyDeviceToHost, c->stream));
     o += hd.P_bytes;
     HIPC(hipMemcpyAsync(o, c->h.phi[(c->step + 1) & 1], hd.P_bytes, hipMemcpyDeviceToHost, c->stream));
+    o += hd.P_bytes;
+    HIPC(hipMemcpyAsync(o, c->h.U[(c->step + 1) & 1], (size_t)c->p.dim * hd.P_bytes, hipMemcpyDeviceToHost,
+                        c->stream));
     HIPC(hipStreamSynchronize(c->stream));
     return PULBM_OK;
 }
@@ -559,7 +565,7 @@ extern "C" int pulbm_restore(pulbm_case* c, const void* buf, size_t bytes)
     if (bytes < sizeof(CkptHeader)) return fail(PULBM_EINVAL, "restart image too short");
     CkptHeader hd;
     std::memcpy(&hd, buf, sizeof hd);
-    if (std::memcmp(hd.magic, kCkptMagic, 8) || hd.version != 2) return fail(PULBM_EINVAL, "not a restart image");
+    if (std::memcmp(hd.magic, kCkptMagic, 8) || hd.version != kCkptVersion) return fail(PULBM_EINVAL, "not a restart image");
     const pulbm_params& q = hd.p;
     const pulbm_params& p = c->p;
     if (q.dim != p.dim || q.nx != p.nx || q.ny != p.ny || q.nz != p.nz || q.store != p.store ||
@@ -581,6 +587,9 @@ extern "C" int pulbm_restore(pulbm_case* c, const void* buf, size_t bytes)
     HIPC(hipMemcpyAsync(c->h.P[c->step & 1], o, hd.P_bytes, hipMemcpyHostToDevice, c->stream));
     o += hd.P_bytes;
     HIPC(hipMemcpyAsync(c->h.phi[(c->step + 1) & 1], o, hd.P_bytes, hipMemcpyHostToDevice, c->stream));
+    o += hd.P_bytes;
+    HIPC(hipMemcpyAsync(c->h.U[(c->step + 1) & 1], o, (size_t)c->p.dim * hd.P_bytes, hipMemcpyHostToDevice,
+                        c->stream));
     HIPC(hipStreamSynchronize(c->stream));
     c->ready = true;
     return PULBM_OK;

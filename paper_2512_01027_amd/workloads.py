@@ -185,6 +185,42 @@ def config_table1_bubble(case, store="fp64"):
     return cfg, (phi, P, u), unit
 
 
+# Head-on binary collision of water droplets in air (Sec. III): relative
+# velocity 2.45 m/s, radius 0.35 mm, surface tension 0.072 N/m, kinematic
+# viscosities 1.51e-5 (air) and 1.00e-6 m^2/s (water), densities 1 and
+# 1000 kg/m^3, so Re = U D / nu_water = 1715 and We = rho_water U^2 D / sigma
+# = 58.4.
+HEAD_ON = {"Re": 1715.0, "We": 58.4, "nu_air_over_water": 15.1}
+
+
+def config_head_on_collision(D=64.0, U=0.04, grid=(256, 192, 192), gap=8.0, store="fp32", q_hydro=19):
+    """Two water droplets of diameter D (nodes) in air approaching along x
+    with relative velocity U (lattice units), periodic box.  The lattice
+    units keep the paper's Re, We and air / water viscosity ratio:
+    nu_water = U D / Re, nu_air = 15.1 nu_water, sigma = rho_water U^2 D / We.
+    D3Q19 for both lattices (the paper's 3D lattice) unless q_hydro = 27.
+    Each droplet moves at U / 2 (weighted by its own phi) and holds the
+    Laplace pressure 2 sigma / R; the droplets start gap nodes apart.
+    Returns cfg, fields and the steps of one time unit D / U."""
+    nx, ny, nz = grid
+    h = HEAD_ON
+    nu_w = U * D / h["Re"]
+    cfg = base_case(3, nx, ny, nz, q_hydro=q_hydro, sigma=1000.0 * U * U * D / h["We"], nu_heavy=nu_w,
+                    nu_light=h["nu_air_over_water"] * nu_w, W=4.0, store=store)
+    x, y, z = _grid(cfg)
+    R = D / 2.0
+    c1 = nx / 2.0 - R - gap / 2.0
+    c2 = nx / 2.0 + R + gap / 2.0
+    rr = (y - ny / 2.0) ** 2 + (z - nz / 2.0) ** 2
+    p1 = tanh_profile(R - np.sqrt((x - c1) ** 2 + rr), cfg["W"])
+    p2 = tanh_profile(R - np.sqrt((x - c2) ** 2 + rr), cfg["W"])
+    phi = np.maximum(p1, p2)
+    P, u = _zero_fields(cfg)
+    P += 2.0 * cfg["sigma"] / R * phi
+    u[0] = 0.5 * U * (p1 - p2)
+    return cfg, (phi, P, u), int(round(D / U))
+
+
 def serving_case(rng, store="fp16", max_nodes=None):
     """One request of the serving stream: 75% 3D (n log-uniform in [32, 192]),
     25% 2D (n log-uniform in [128, 1024]); static droplet or rising bubble;

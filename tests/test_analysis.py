@@ -52,3 +52,59 @@ def test_rise_velocity_of_uniform_flow():
     cfg = W.base_case(2, 64, 80)
     phi, _, u = W.droplet(cfg, 10.0, heavy_inside=False, u0=(0.01, -0.02))
     assert A.rise_velocity(phi[0], u[:, 0]) == pytest.approx((0.01, -0.02), rel=1e-12)
+
+
+def _spheres(shape, centers, R, width=4.0):
+    nz, ny, nx = shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    phi = np.zeros(shape)
+    for cx, cy, cz in centers:
+        d = R - np.sqrt((x - cx) ** 2 + (y - cy) ** 2 + (z - cz) ** 2)
+        phi = np.maximum(phi, 0.5 + 0.5 * np.tanh(2 * d / width))
+    return phi
+
+
+def test_droplet_count_separate_touching_and_wrapped():
+    shape = (24, 24, 48)
+    assert A.droplet_count(np.zeros(shape)) == 0
+    assert A.droplet_count(_spheres(shape, [(12, 12, 12), (36, 12, 12)], 6.0)) == 2
+    # overlapping spheres are one piece
+    assert A.droplet_count(_spheres(shape, [(20, 12, 12), (28, 12, 12)], 6.0)) == 1
+    # a sphere across the periodic x edge is one piece, not two
+    assert A.droplet_count(_spheres(shape, [(1, 12, 12), (49, 12, 12)], 6.0)) == 1
+    # a sphere across the y and z edges as well
+    phi = np.roll(np.roll(_spheres(shape, [(24, 12, 12)], 6.0), 12, axis=0), 12, axis=1)
+    assert A.droplet_count(phi) == 1
+    # three pieces: the satellite between two large ones
+    assert A.droplet_count(_spheres(shape, [(8, 12, 12), (24, 12, 12), (40, 12, 12)], 3.0)) == 3
+
+
+def test_collision_extent_of_a_sphere_and_a_disc():
+    shape = (40, 40, 60)
+    r, L = A.collision_extent(_spheres(shape, [(30, 20, 20)], 10.0))
+    # phi >= 1/2 inside the radius: farthest node within one node of R
+    assert 9.0 <= r <= 10.0 and 19 <= L <= 21
+    z, y, x = np.meshgrid(np.arange(40), np.arange(40), np.arange(60), indexing="ij")
+    disc = ((np.abs(x - 30) < 2.5) & ((y - 20) ** 2 + (z - 20) ** 2 <= 15.0 ** 2)).astype(float)
+    r, L = A.collision_extent(disc)
+    assert 14.0 <= r <= 15.0 and L == 5
+
+
+def test_max_air_speed_ignores_water():
+    phi = np.zeros((4, 4, 4))
+    phi[:2] = 1.0
+    u = np.zeros((3, 4, 4, 4))
+    u[0, :2] = 0.5      # water
+    u[1, 2:] = 0.03     # air
+    assert A.max_air_speed(phi, u) == pytest.approx(0.03)
+
+
+def test_head_on_config_keeps_reynolds_and_weber():
+    cfg, (phi, P, u), unit = W.config_head_on_collision(D=20.0, U=0.05, grid=(64, 32, 32))
+    D, U = 20.0, 0.05
+    assert U * D / cfg["nu_heavy"] == pytest.approx(1715.0)
+    assert cfg["rho_heavy"] * U * U * D / cfg["sigma"] == pytest.approx(58.4)
+    assert cfg["nu_light"] / cfg["nu_heavy"] == pytest.approx(15.1)
+    assert unit == 400 and A.droplet_count(phi) == 2
+    # the droplets approach each other at U / 2 each
+    assert u[0].max() == pytest.approx(U / 2, rel=1e-3) and u[0].min() == pytest.approx(-U / 2, rel=1e-3)
