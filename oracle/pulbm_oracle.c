@@ -39,6 +39,22 @@
  *      u* odd in its flow part and even in its body-force part,
  *      P extrapolated hydrostatically P(m) + rho(x) g.(ghost - m).
  *  R12 phi = 1 is the heavy fluid; rho_ref = rho_light.
+ *  R15 solid block (the dam-break obstacle of Sec. III): its nodes carry no
+ *      fluid.  A link from a fluid node into the block bounces back as at a
+ *      wall (R11).  A stencil value at a block node mirrors it across each
+ *      of its faces that is exposed to fluid (a face node across one, an edge
+ *      node across two, a corner node across three), with the parities and
+ *      the hydrostatic pressure of R11 counted once per face crossed.
+ *  R16 open top at fixed pressure (the dam break's atmospheric top, Sec. III;
+ *      the paper gives no scheme): beyond the high end of the last axis,
+ *      phi, rho, u and u* take the value of the nearest node (zero normal
+ *      gradient) and the pressure the value 2 p_top - P(m), so that P is
+ *      p_top on the boundary half a link out.  A hydrodynamic population
+ *      leaving through the top is gone, and the opposite one entering the top
+ *      node is that node's own equilibrium g^eq of the step.  The phase field
+ *      is closed there (h bounces back as at a wall): phi's mass stays exact,
+ *      and the sharpening flux theta n of the air side (with delta theta on
+ *      wherever phi > 0) cannot pump phi in through the boundary.
  */
 #include "pulbm_oracle.h"
 
@@ -81,6 +97,7 @@ struct pulbm_oracle_case {
     double *J;           /* velocity moment of the populations (work array) */
     double *Ps;          /* pressure the populations carry, rho_ref T sum g (work) */
     double *phi, *rho, *P, *u;
+    unsigned char* solid; /* 1 at nodes of the block (R15) */
     int64_t step;
 };
 
@@ -133,6 +150,23 @@ static int model_init(model* m, const pulbm_oracle_params* p)
     if (!(p->rho_heavy > 0) || !(p->rho_light > 0) || !(p->W > 0) || !(p->M > 0)) return -1;
     if (!(p->nu_heavy > 0) || !(p->nu_light > 0) || p->rho_heavy == p->rho_light) return -1;
     if (p->collision != 0 && p->collision != 1) return -1;
+    const int nn[3] = {p->nx, p->ny, p->nz};
+    for (int a = 0; a < 3; ++a) {
+        if (p->wall[a] < 0 || p->wall[a] > 2) return -1;
+        if (p->wall[a] == 2 && a != p->dim - 1) return -1;  /* open end: last axis only */
+    }
+    int has_block = 1;
+    for (int a = 0; a < 3; ++a)
+        if (p->block_lo[a] >= p->block_hi[a]) has_block = 0;
+    if (has_block) {
+        for (int a = 0; a < 3; ++a) {
+            int lo = p->block_lo[a], hi = p->block_hi[a];
+            int full = lo == 0 && hi == nn[a];
+            if (lo < 0 || hi > nn[a]) return -1;
+            if (!full && hi - lo < 2) return -1;  /* faces on both sides need 2 layers */
+            if (!full && !p->wall[a] && (lo < 1 || hi > nn[a] - 1)) return -1;  /* no wrap */
+        }
+    }
     if (build_lattice(&m->G, p->dim, p->q_hydro)) return -1;
     if (build_lattice(&m->H, p->dim, p->q_phase)) return -1;
     m->p = *p;
@@ -153,12 +187,25 @@ static size_t idx3(const pulbm_oracle_case* C, const int x[3])
     return (size_t)x[0] + (size_t)C->n[0] * ((size_t)x[1] + (size_t)C->n[1] * (size_t)x[2]);
 }
 
+static int in_block(const pulbm_oracle_case* C, const int m[3])
+{
+    const int32_t *lo = C->m.p.block_lo, *hi = C->m.p.block_hi;
+    for (int a = 0; a < 3; ++a)
+        if (lo[a] >= hi[a] || m[a] < lo[a] || m[a] >= hi[a]) return 0;
+    return 1;
+}
+
 /* Target of displacement d from node x.  Periodic axes wrap.  On a wall axis a
  * target outside the box is a ghost: its mirror m is the nearest fluid node on
- * that axis and off = ghost - m.  Returns the number of wall axes crossed. */
-static int resolve(const pulbm_oracle_case* C, const int x[3], const int d[3], int m[3], int off[3])
+ * that axis and off = ghost - m.  A target in the solid block is mirrored
+ * across each exposed face it lies on (R15).  Returns the number of walls and
+ * block faces crossed; *open (if given) is set when the target lies beyond an
+ * open top (R16), which is not counted as a crossing. */
+static int resolve(const pulbm_oracle_case* C, const int x[3], const int d[3], int m[3], int off[3],
+                   int* open)
 {
     int crossed = 0;
+    if (open) *open = 0;
     for (int a = 0; a < 3; ++a) {
         int t = x[a] + d[a], n = C->n[a];
         off[a] = 0;
@@ -166,13 +213,32 @@ static int resolve(const pulbm_oracle_case* C, const int x[3], const int d[3], i
             if (C->m.p.wall[a]) {
                 int mm = t < 0 ? 0 : n - 1;
                 off[a] = t - mm;
+                if (C->m.p.wall[a] == 2 && t >= n) {
+                    if (open) *open = 1;
+                } else {
+                    ++crossed;
+                }
                 t = mm;
-                ++crossed;
             } else {
                 t = ((t % n) + n) % n;
             }
         }
         m[a] = t;
+    }
+    if (in_block(C, m)) {
+        const int32_t *lo = C->m.p.block_lo, *hi = C->m.p.block_hi;
+        int r[3] = {m[0], m[1], m[2]};
+        for (int a = 0; a < 3; ++a) {
+            if (m[a] == lo[a] && lo[a] >= 1) {
+                r[a] = lo[a] - 1;
+                ++crossed;
+            } else if (m[a] == hi[a] - 1 && hi[a] <= C->n[a] - 1) {
+                r[a] = hi[a];
+                ++crossed;
+            }
+            off[a] += m[a] - r[a];
+        }
+        for (int a = 0; a < 3; ++a) m[a] = r[a];
     }
     return crossed;
 }
@@ -181,7 +247,7 @@ static int resolve(const pulbm_oracle_case* C, const int x[3], const int d[3], i
 static double even_at(const pulbm_oracle_case* C, const double* f, const int x[3], const int d[3])
 {
     int m[3], off[3];
-    resolve(C, x, d, m, off);
+    resolve(C, x, d, m, off, NULL);
     return f[idx3(C, m)];
 }
 
@@ -190,18 +256,20 @@ static double even_at(const pulbm_oracle_case* C, const double* f, const int x[3
 static double odd_at(const pulbm_oracle_case* C, const double* f, const int x[3], const int d[3])
 {
     int m[3], off[3];
-    int k = resolve(C, x, d, m, off);
+    int k = resolve(C, x, d, m, off, NULL);
     double v = f[idx3(C, m)];
     return (k & 1) ? -v : v;
 }
 
-/* Pressure: a ghost is extrapolated hydrostatically from its mirror. */
+/* Pressure: a ghost is extrapolated hydrostatically from its mirror; beyond
+ * an open top it is 2 p_top - P(m) (R16). */
 static double pres_at(const pulbm_oracle_case* C, const double* P, const int x[3], const int d[3],
                       double rho_x)
 {
-    int m[3], off[3];
-    int k = resolve(C, x, d, m, off);
+    int m[3], off[3], open;
+    int k = resolve(C, x, d, m, off, &open);
     double v = P[idx3(C, m)];
+    if (open) return 2.0 * C->m.p.p_top - v;
     if (k) {
         const double* gv = C->m.p.gravity;
         v += rho_x * (gv[0] * off[0] + gv[1] * off[1] + gv[2] * off[2]);
@@ -236,7 +304,7 @@ static double ustar_at(const pulbm_oracle_case* C, const double* J, int a, const
                        const int d[3])
 {
     int m[3], off[3];
-    int k = resolve(C, x, d, m, off);
+    int k = resolve(C, x, d, m, off, NULL);
     double v = J[(size_t)a * C->N + idx3(C, m)];
     if (k & 1) v = -v + 2.0 * C->m.p.gravity[a];
     return v;
@@ -258,9 +326,21 @@ static void moments(const pulbm_oracle_case* C, double* phi, double* rho, double
     const size_t N = C->N;
     double* J = C->J;
     double* Ps = C->Ps;
-    /* pass 1: phi, rho, u*, P* */
+    /* pass 1: phi, rho, u*, P*; block nodes hold no fluid (phi = 0, u = 0,
+     * P = 0) */
 #pragma omp parallel for schedule(static)
     for (size_t n = 0; n < N; ++n) {
+        if (C->solid[n]) {
+            phi[n] = 0.0;
+            rho[n] = ra;
+            P[n] = 0.0;
+            Ps[n] = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                J[(size_t)a * N + n] = 0.0;
+                if (a < dim) u[(size_t)a * N + n] = 0.0;
+            }
+            continue;
+        }
         double ph = 0.0;
         for (int j = 0; j < H->q; ++j) ph += C->h[(size_t)j * N + n];
         double r, tau;
@@ -283,6 +363,7 @@ static void moments(const pulbm_oracle_case* C, double* phi, double* rho, double
             for (int xx = 0; xx < C->n[0]; ++xx) {
                 int x[3] = {xx, y, z};
                 size_t n = idx3(C, x);
+                if (C->solid[n]) continue;
                 double r = rho[n];
                 double omega = (r - ra) / (rw - ra) * (M->omega_max - 1.0);
                 double s1 = 0.0, s2 = 0.0;
@@ -303,6 +384,7 @@ static void moments(const pulbm_oracle_case* C, double* phi, double* rho, double
             for (int xx = 0; xx < C->n[0]; ++xx) {
                 int x[3] = {xx, y, z};
                 size_t n = idx3(C, x);
+                if (C->solid[n]) continue;
                 double uu[3] = {0.0, 0.0, 0.0};
                 for (int i = 0; i < G->q; ++i) {
                     double K = k_term(C, P, x, i, rho[n]);
@@ -450,6 +532,7 @@ static void collide_stream(pulbm_oracle_case* C)
             for (int xx = 0; xx < C->n[0]; ++xx) {
                 int x[3] = {xx, y, z};
                 size_t n = idx3(C, x);
+                if (C->solid[n]) continue;
                 nodevals v;
                 node_values(C, x, &v);
                 double heq[27], geq[27], F[3], rho, tau;
@@ -487,17 +570,24 @@ static void collide_stream(pulbm_oracle_case* C)
                     gs[i] = geq[i] + (1.0 - 1.0 / tau) * phipi;
                 }
                 }
-                /* Streaming: push to x + c; at a wall, reflect into the opposite slot. */
+                /* Streaming: push to x + c; at a wall or the block, reflect into
+                 * the opposite slot; through an open top, h reflects (no phi
+                 * crosses it) and the opposite g slot takes this node's
+                 * equilibrium (R16). */
                 for (int j = 0; j < H->q; ++j) {
-                    int m[3], off[3];
-                    if (resolve(C, x, H->c[j], m, off))
+                    int m[3], off[3], open;
+                    int k = resolve(C, x, H->c[j], m, off, &open);
+                    if (k || open)
                         C->hn[(size_t)H->opp[j] * N + n] = hs[j];
                     else
                         C->hn[(size_t)j * N + idx3(C, m)] = hs[j];
                 }
                 for (int i = 0; i < G->q; ++i) {
-                    int m[3], off[3];
-                    if (resolve(C, x, G->c[i], m, off)) {
+                    int m[3], off[3], open;
+                    int k = resolve(C, x, G->c[i], m, off, &open);
+                    if (open) {
+                        C->gn[(size_t)G->opp[i] * N + n] = geq[G->opp[i]];
+                    } else if (k) {
                         double cF = 0.0;
                         for (int a = 0; a < dim; ++a) cF += G->c[i][a] * F[a];
                         C->gn[(size_t)G->opp[i] * N + n] = gs[i] - 2.0 * G->w[i] * cF / (rho * T);
@@ -537,11 +627,18 @@ int pulbm_oracle_create(const pulbm_oracle_params* p, pulbm_oracle_case** out)
     C->rho = (double*)calloc(N, sizeof(double));
     C->P = (double*)calloc(N, sizeof(double));
     C->u = (double*)calloc(3 * N, sizeof(double));
+    C->solid = (unsigned char*)calloc(N, 1);
     if (!C->h || !C->hn || !C->g || !C->gn || !C->Plag || !C->J || !C->Ps || !C->phi || !C->rho ||
-        !C->P || !C->u) {
+        !C->P || !C->u || !C->solid) {
         pulbm_oracle_destroy(C);
         return -2;
     }
+    for (int z = 0; z < C->n[2]; ++z)
+        for (int y = 0; y < C->n[1]; ++y)
+            for (int xx = 0; xx < C->n[0]; ++xx) {
+                int x[3] = {xx, y, z};
+                C->solid[idx3(C, x)] = (unsigned char)in_block(C, x);
+            }
     *out = C;
     return 0;
 }
@@ -560,6 +657,7 @@ void pulbm_oracle_destroy(pulbm_oracle_case* C)
     free(C->rho);
     free(C->P);
     free(C->u);
+    free(C->solid);
     free(C);
 }
 
@@ -573,19 +671,25 @@ int pulbm_oracle_init_fields(pulbm_oracle_case* C, const double* phi, const doub
     const size_t N = C->N;
     for (size_t n = 0; n < N; ++n) {
         double tau;
-        C->phi[n] = phi[n];
-        phase_props(M, phi[n], &C->rho[n], &tau);
-        C->P[n] = P[n];
-        C->Plag[n] = P[n];
+        const int s = C->solid[n];
+        C->phi[n] = s ? 0.0 : phi[n];
+        phase_props(M, C->phi[n], &C->rho[n], &tau);
+        C->P[n] = s ? 0.0 : P[n];
+        C->Plag[n] = C->P[n];
     }
     memset(C->u, 0, 3 * N * sizeof(double));
     for (int a = 0; a < dim; ++a)
-        for (size_t n = 0; n < N; ++n) C->u[(size_t)a * N + n] = u[(size_t)a * N + n];
+        for (size_t n = 0; n < N; ++n) C->u[(size_t)a * N + n] = C->solid[n] ? 0.0 : u[(size_t)a * N + n];
     for (int z = 0; z < C->n[2]; ++z)
         for (int y = 0; y < C->n[1]; ++y)
             for (int xx = 0; xx < C->n[0]; ++xx) {
                 int x[3] = {xx, y, z};
                 size_t n = idx3(C, x);
+                if (C->solid[n]) {  /* block nodes hold no populations */
+                    for (int j = 0; j < M->H.q; ++j) C->h[(size_t)j * N + n] = 0.0;
+                    for (int i = 0; i < M->G.q; ++i) C->g[(size_t)i * N + n] = 0.0;
+                    continue;
+                }
                 nodevals v;
                 node_values(C, x, &v);
                 double heq[27], geq[27], F[3], rho, tau;

@@ -26,7 +26,9 @@ extern "C" {
 typedef struct {
     int32_t dim, nx, ny, nz;      /* nz = 1 in 2D                                  */
     int32_t q_hydro, q_phase;     /* 2D: 9/9; 3D: hydro 19|27, phase 19|27         */
-    int32_t wall[3];              /* per axis: 0 periodic, 1 halfway bounce-back   */
+    int32_t wall[3];              /* per axis: 0 periodic, 1 halfway bounce-back at
+                                     both ends, 2 (last axis only) bounce-back at
+                                     the low end, pressure p_top at the high end   */
     int32_t delta_theta;          /* 1: apply the anti-rarefaction correction      */
     int32_t collision;            /* hydro collision: 0 filter (Eq. LB_filter_col),
                                      1 BGK (Eq. BGK_LBeq_hydroeq)                  */
@@ -35,6 +37,9 @@ typedef struct {
     double sigma, W, M;           /* surface tension, interface width, mobility    */
     double lambda_bulk;           /* bulk viscosity (1/6 in the paper)             */
     double gravity[3];            /* body force per unit mass: F_ext = rho * g     */
+    int32_t block_lo[3], block_hi[3]; /* solid block, nodes lo <= x < hi per axis;
+                                     none when lo >= hi on any axis               */
+    double p_top;                 /* pressure of an open high end (wall = 2)       */
 } pulbm_oracle_params;
 
 typedef struct {
