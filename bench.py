@@ -19,8 +19,9 @@ Printed as one JSON line:
   d3q19_hydro    the same workload on D3Q19 for the hydrodynamic populations
                  too (the lattice of the paper's 3D runs), FP32 and FP16
   workloads      throughput at the real sizes of the 3D rising bubble (256^3,
-                 walls in z; FP32, FP16 and BF16 storage) and the dam break
-                 (512 x 256 x 256, walls on all faces; FP16 and FP32)
+                 walls in z; FP32, FP16 and BF16 storage), the dam break
+                 (512 x 256 x 256, walls on all faces; FP16 and FP32) and the
+                 dam break against a block with an open top (585 x 182 x 182)
   serving        a seeded Poisson stream of droplet / bubble requests served
                  by continuous batching, p50 / p99 latency and aggregate MLUPS,
                  beside the same stream run one case at a time
@@ -205,7 +206,8 @@ def workloads_leg(steps=100, warmup=10):
     from paper_2512_01027_amd import workloads as W
 
     runs = [("rising_bubble_256cube", lambda st: W.config_rising_bubble_3d(256, store=st), ("fp32", "fp16", "bf16")),
-            ("dam_break_512x256x256", lambda st: W.config_dam_break_3d(store=st), ("fp16", "fp32"))]
+            ("dam_break_512x256x256", lambda st: W.config_dam_break_3d(store=st), ("fp16", "fp32")),
+            ("dam_break_block_585x182x182", lambda st: W.config_dam_break_block(store=st), ("fp16", "fp32"))]
     out = {}
     for name, make, stores in runs:
         leg = {}

@@ -59,7 +59,10 @@ typedef struct {
                                     nodes in FP64 storage, below 2^29 otherwise             */
     int32_t q_hydro, q_phase;    /* 2D: 9, 9; 3D: 27 or 19, 19 (hydro D3Q27, or D3Q19 as the
                                     paper's 3D runs; phase field D3Q19)                      */
-    int32_t wall[3];             /* per axis: 0 periodic, 1 no-slip walls at both ends      */
+    int32_t wall[3];             /* per axis: 0 periodic, 1 no-slip walls at both ends, 2
+                                    (last axis only) a wall at the low end and an open end
+                                    at pressure p_top at the high end (the dam break's
+                                    atmospheric top, Sec. III)                              */
     int32_t delta_theta;         /* 1: apply the delta-theta correction of Sec. II [1]      */
     int32_t store;               /* PULBM_STORE_*                                           */
     int32_t collision;           /* hydrodynamic collision: 0 the filter collision of Sec. II
@@ -70,6 +73,13 @@ typedef struct {
     double sigma, W, M;          /* surface tension, interface width, mobility [M = 0.166]  */
     double lambda_bulk;          /* bulk viscosity [1/6]                                    */
     double gravity[3];           /* body force per unit mass, F_ext = rho g                 */
+    int32_t block_lo[3], block_hi[3]; /* solid block (the dam break's obstacle, Sec. III):
+                                    nodes lo <= x < hi on every axis; none if lo >= hi on
+                                    any axis.  At least 2 nodes thick (or spanning the
+                                    axis); not across a periodic boundary; not touching
+                                    an open end.  Its nodes carry no fluid and read back
+                                    phi = P = u = 0.                                        */
+    double p_top;                /* pressure at an open end (wall = 2)                      */
 } pulbm_params;
 
 typedef struct {

@@ -165,6 +165,7 @@ static int model_init(model* m, const pulbm_oracle_params* p)
             if (lo < 0 || hi > nn[a]) return -1;
             if (!full && hi - lo < 2) return -1;  /* faces on both sides need 2 layers */
             if (!full && !p->wall[a] && (lo < 1 || hi > nn[a] - 1)) return -1;  /* no wrap */
+            if (p->wall[a] == 2 && hi == nn[a]) return -1;  /* clear of the open end */
         }
     }
     if (build_lattice(&m->G, p->dim, p->q_hydro)) return -1;

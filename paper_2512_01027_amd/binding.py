@@ -45,6 +45,7 @@ class Params(C.Structure):
         ("nu_heavy", C.c_double), ("nu_light", C.c_double),
         ("sigma", C.c_double), ("W", C.c_double), ("M", C.c_double),
         ("lambda_bulk", C.c_double), ("gravity", C.c_double * 3),
+        ("block_lo", C.c_int32 * 3), ("block_hi", C.c_int32 * 3), ("p_top", C.c_double),
     ]
 
 
@@ -145,6 +146,12 @@ def make_params(cfg: dict) -> Params:
     gv = list(cfg.get("gravity", (0.0, 0.0, 0.0))) + [0.0, 0.0, 0.0]
     for a in range(3):
         p.gravity[a] = float(gv[a])
+    # solid block ((lo_x, lo_y, lo_z), (hi_x, hi_y, hi_z)): nodes lo <= x < hi
+    blk = cfg.get("block")
+    for a in range(3):
+        p.block_lo[a] = int(blk[0][a]) if blk else 0
+        p.block_hi[a] = int(blk[1][a]) if blk else 0
+    p.p_top = float(cfg.get("p_top", 0.0))
     return p
 
 

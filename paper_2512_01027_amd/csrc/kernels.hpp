@@ -66,6 +66,10 @@ struct CaseDev {
     double rho_a, rho_w, tau_a, tau_w, tau_phi, M, W, sigma, lambda_b;
     double grav[3];
     double h_scale, h_inv_scale, g_scale, g_inv_scale;
+    double p_top;           // pressure of an open high end (wall = 2 on the last axis)
+    int32_t blk_lo[3], blk_hi[3];  // solid block, nodes lo <= x < hi (has_block)
+    int32_t has_block;
+    int32_t pad1;
 };
 
 using CDesc = const PULBM_CST CaseDev;
@@ -179,7 +183,16 @@ template <class T> __device__ __forceinline__ PULBM_GLB T* at_node(void* p, uint
 struct Nav {
     int o[3][3];
     uint32_t solid;  // bit 2a: the -1 step on axis a is outside a wall; bit 2a+1: the +1 step
+    uint32_t open;   // the same bits for a step out through an open end
+    uint32_t blk[3]; // bit k: coordinate + k - 1 on axis a lies in the block's range
 };
+
+// Is node (x, y, z) inside the solid block?
+__device__ __forceinline__ bool in_block(CDesc& cs, int x, int y, int z)
+{
+    return cs.has_block && x >= cs.blk_lo[0] && x < cs.blk_hi[0] && y >= cs.blk_lo[1] && y < cs.blk_hi[1] &&
+           z >= cs.blk_lo[2] && z < cs.blk_hi[2];
+}
 
 __device__ __forceinline__ Nav make_nav(CDesc& cs, int x, int y, int z, int esz)
 {
@@ -188,6 +201,7 @@ __device__ __forceinline__ Nav make_nav(CDesc& cs, int x, int y, int z, int esz)
     const int n[3] = {cs.nx, cs.ny, cs.nz};
     const int st[3] = {esz, esz * cs.nx, esz * cs.nx * cs.ny};
     v.solid = 0;
+    v.open = 0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         v.o[a][1] = 0;
@@ -195,7 +209,18 @@ __device__ __forceinline__ Nav make_nav(CDesc& cs, int x, int y, int z, int esz)
         v.o[a][2] = (p[a] == n[a] - 1) ? -(n[a] - 1) * st[a] : st[a];
         if (cs.wall[a]) {
             if (p[a] == 0) v.solid |= 1u << (2 * a);
-            if (p[a] == n[a] - 1) v.solid |= 1u << (2 * a + 1);
+            if (p[a] == n[a] - 1) {
+                if (cs.wall[a] == 2) v.open |= 1u << (2 * a + 1);
+                else v.solid |= 1u << (2 * a + 1);
+            }
+        }
+        // a block spanning a whole periodic axis holds every coordinate
+        const bool full = cs.blk_lo[a] == 0 && cs.blk_hi[a] == n[a];
+        v.blk[a] = 0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int q = p[a] + k - 1;
+            if (cs.has_block && (full || (q >= cs.blk_lo[a] && q < cs.blk_hi[a]))) v.blk[a] |= 1u << k;
         }
     }
     return v;
@@ -207,8 +232,7 @@ __device__ __forceinline__ int nav_off(const Nav& v, int i, int sgn)
     return v.o[0][sgn * L::c(i, 0) + 1] + v.o[1][sgn * L::c(i, 1) + 1] + v.o[2][sgn * L::c(i, 2) + 1];
 }
 
-template <class L>
-__device__ __forceinline__ bool nav_solid(const Nav& v, int i, int sgn)
+template <class L> __device__ __forceinline__ uint32_t nav_mask(int i, int sgn)
 {
     uint32_t m = 0;
 #pragma unroll
@@ -217,16 +241,36 @@ __device__ __forceinline__ bool nav_solid(const Nav& v, int i, int sgn)
         if (ca == -1) m |= 1u << (2 * a);
         if (ca == 1) m |= 1u << (2 * a + 1);
     }
-    return (v.solid & m) != 0;
+    return m;
 }
 
-// Does the tile (or its ghost layer) touch a wall?  Uniform per block; tiles
-// that do not skip every bounce-back test.
+// Does the step along sgn c_i leave through the open end?
+template <class L>
+__device__ __forceinline__ bool nav_open(const Nav& v, int i, int sgn)
+{
+    return (v.open & nav_mask<L>(i, sgn)) != 0;
+}
+
+// Does the step along sgn c_i leave the fluid (through a wall or the open
+// end, or into the block)?  Its population then stays at the node, in the
+// slot of the opposite direction.
+template <class L>
+__device__ __forceinline__ bool nav_solid(const Nav& v, int i, int sgn)
+{
+    const bool blk = ((v.blk[0] >> (sgn * L::c(i, 0) + 1)) & (v.blk[1] >> (sgn * L::c(i, 1) + 1)) &
+                      (v.blk[2] >> (sgn * L::c(i, 2) + 1)) & 1u) != 0;
+    return ((v.solid | v.open) & nav_mask<L>(i, sgn)) != 0 || blk;
+}
+
+// Does the tile (or its ghost layer) touch a wall, the open end or the
+// block?  Uniform per block; tiles that do not skip every boundary test.
 template <class Mo>
 __device__ __forceinline__ bool tile_at_wall(CDesc& cs, int ox, int oy, int oz)
 {
+    const bool blk = cs.has_block && ox - 1 < cs.blk_hi[0] && ox + Mo::TX >= cs.blk_lo[0] && oy - 1 < cs.blk_hi[1] &&
+                     oy + Mo::TY >= cs.blk_lo[1] && oz - 1 < cs.blk_hi[2] && oz + Mo::TZ >= cs.blk_lo[2];
     return (cs.wall[0] && (ox == 0 || ox + Mo::TX >= cs.nx)) || (cs.wall[1] && (oy == 0 || oy + Mo::TY >= cs.ny)) ||
-           (cs.wall[2] && (oz == 0 || oz + Mo::TZ >= cs.nz));
+           (cs.wall[2] && (oz == 0 || oz + Mo::TZ >= cs.nz)) || blk;
 }
 
 // Population loads and stores.  The populations of a step are read once and
@@ -278,7 +322,10 @@ __device__ __forceinline__ void aa_store(const Slots<S>& f, uint32_t nb, const N
 // ---------------------------------------------------------- tile regions
 
 // Resolve global coordinate t on an axis of n nodes: periodic wrap, or the
-// mirror node of a ghost outside a wall (off = t - mirror).
+// mirror node of a ghost outside a wall (off = t - mirror).  A ghost beyond
+// an open end (wall = 2, high side) takes the nearest node too, marked by
+// kOpenGhost in *crossed instead of counting as a wall crossing.
+constexpr int kOpenGhost = 256;
 __device__ __forceinline__ int resolve_axis(int t, int n, int wall, int* off, int* crossed)
 {
     *off = 0;
@@ -286,7 +333,7 @@ __device__ __forceinline__ int resolve_axis(int t, int n, int wall, int* off, in
     if (wall) {
         const int m = t < 0 ? 0 : n - 1;
         *off = t - m;
-        *crossed += 1;
+        *crossed += (wall == 2 && t >= n) ? kOpenGhost : 1;
         return m;
     }
     t %= n;
@@ -305,14 +352,34 @@ struct Halo1 {
     static constexpr int ZH = DIMV == 3 ? 1 : 0;
     static constexpr int RX = Mo::TX + 2, RY = Mo::TY + 2, RZ = Mo::TZ + 2 * ZH;
     using R = Region<RX, RY, RZ>;
+    // BND: the tile touches a wall, the open end or the block (tiles that do
+    // not never meet the block, and skip its test)
+    template <bool BND = true>
     __device__ static __forceinline__ uint32_t cell(CDesc& cs, const TileCtx& t, int k, int off[3], int* cr)
     {
         const int ix = k % RX, iy = (k / RX) % RY, iz = k / (RX * RY);
         *cr = 0;
-        const int mx = resolve_axis(t.ox - 1 + ix, cs.nx, cs.wall[0], &off[0], cr);
-        const int my = resolve_axis(t.oy - 1 + iy, cs.ny, cs.wall[1], &off[1], cr);
-        const int mz = resolve_axis(t.oz - ZH + iz, cs.nz, cs.wall[2], &off[2], cr);
-        return (uint32_t)mx + (uint32_t)cs.nx * ((uint32_t)my + (uint32_t)cs.ny * (uint32_t)mz);
+        int m[3];
+        m[0] = resolve_axis(t.ox - 1 + ix, cs.nx, cs.wall[0], &off[0], cr);
+        m[1] = resolve_axis(t.oy - 1 + iy, cs.ny, cs.wall[1], &off[1], cr);
+        m[2] = resolve_axis(t.oz - ZH + iz, cs.nz, cs.wall[2], &off[2], cr);
+        if (BND && in_block(cs, m[0], m[1], m[2])) {
+            // a block node mirrors across each exposed face it lies on
+            const int n[3] = {cs.nx, cs.ny, cs.nz};
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                if (m[a] == cs.blk_lo[a] && cs.blk_lo[a] >= 1) {
+                    m[a] -= 1;
+                    off[a] += 1;
+                    *cr += 1;
+                } else if (m[a] == cs.blk_hi[a] - 1 && cs.blk_hi[a] <= n[a] - 1) {
+                    m[a] += 1;
+                    off[a] -= 1;
+                    *cr += 1;
+                }
+            }
+        }
+        return (uint32_t)m[0] + (uint32_t)cs.nx * ((uint32_t)m[1] + (uint32_t)cs.ny * (uint32_t)m[2]);
     }
 };
 
@@ -736,8 +803,26 @@ __global__ __launch_bounds__(256) void k_moments(CaseTab cases, const int* hdr, 
     const int x = t.ox + lx, y = t.oy + ly, z = t.oz + lz;
     if (x >= cs.nx || y >= cs.ny || z >= cs.nz) return;
     const bool odd = t.step & 1;
-    if (tile_at_wall<Mo>(cs, t.ox, t.oy, t.oz)) moments_node<LS, S, true>(cs, x, y, z, odd);
-    else moments_node<LS, S, false>(cs, x, y, z, odd);
+    if (tile_at_wall<Mo>(cs, t.ox, t.oy, t.oz)) {
+        if (in_block(cs, x, y, z)) {
+            // block nodes carry no fluid: phi, u*, P*, M2 = 0
+            using CT = typename Codec<S>::CT;
+            constexpr int DIMV = Model<LS>::DIM;
+            const uint32_t n = (uint32_t)x + (uint32_t)cs.nx * ((uint32_t)y + (uint32_t)cs.ny * (uint32_t)z);
+            const uint32_t na = n * (uint32_t)sizeof(CT);
+            *at_node<CT>(cs.phi[odd ? 1 : 0], n) = 0;
+            *at_node<CT>(cs.Ps, n) = 0;
+            const Slots<CT> Js = slots<CT>(cs.J, cs.N), Ms = slots<CT>(cs.M2, cs.N);
+#pragma unroll
+            for (int a = 0; a < DIMV; ++a) *Js.at(a, na) = 0;
+#pragma unroll
+            for (int k = 0; k < (DIMV == 2 ? 3 : 6); ++k) *Ms.at(k, na) = 0;
+            return;
+        }
+        moments_node<LS, S, true>(cs, x, y, z, odd);
+    } else {
+        moments_node<LS, S, false>(cs, x, y, z, odd);
+    }
 }
 
 // --- pressure (Sec. II): P = rho_ref T sum_i (g_i + (1 + omega) K_i)
@@ -761,10 +846,15 @@ __device__ __forceinline__ void pressure_tile(CDesc& cs, const TileCtx& t, AT* s
         const int k = threadIdx.x + 256 * it;
         if (k >= R::N) break;
         int off[3], cr;
-        const uint32_t m = HR::cell(cs, t, k, off, &cr);
+        const uint32_t m = HR::template cell<WALL>(cs, t, k, off, &cr);
         sP[k] = *at_node<AT>(cs.Ps, m);
-        // ghost pressure = P(mirror) + rho(x) g.(ghost - mirror): keep g.off
+        // ghost pressure = P(mirror) + rho(x) g.(ghost - mirror): keep g.off;
+        // beyond the open end 2 p_top - P(mirror), p_top half a link out
         if (WALL) sGD[k] = (AT)(cs.grav[0] * off[0] + cs.grav[1] * off[1] + cs.grav[2] * off[2]);
+        if (WALL && (cr & kOpenGhost)) {
+            sP[k] = (AT)(2.0 * cs.p_top - (double)sP[k]);
+            sGD[k] = 0;
+        }
 #pragma unroll
         for (int a = 0; a < DIMV; ++a) {
             AT j = *Js.at(a, m * (uint32_t)sizeof(AT));
@@ -779,6 +869,10 @@ __device__ __forceinline__ void pressure_tile(CDesc& cs, const TileCtx& t, AT* s
     const int x = t.ox + lx, y = t.oy + ly, z = t.oz + lz;
     if (x >= cs.nx || y >= cs.ny || z >= cs.nz) return;
     const uint32_t n = (uint32_t)x + (uint32_t)cs.nx * ((uint32_t)y + (uint32_t)cs.ny * (uint32_t)z);
+    if (WALL && in_block(cs, x, y, z)) {
+        *at_node<AT>(cs.P[(t.step + 1) & 1], n) = 0;
+        return;
+    }
     const double phi = (double)*at_node<AT>(cs.phi[t.step & 1], n);
     const double ra = cs.rho_a, rw = cs.rho_w;
     const double pc = phi < 0.0 ? 0.0 : (phi > 1.0 ? 1.0 : phi);
@@ -834,9 +928,13 @@ __device__ __forceinline__ void velocity_tile(CDesc& cs, const TileCtx& t, CT* s
         const int k = threadIdx.x + 256 * it;
         if (k >= R::N) break;
         int off[3], cr;
-        const uint32_t m = HR::cell(cs, t, k, off, &cr);
+        const uint32_t m = HR::template cell<WALL>(cs, t, k, off, &cr);
         sP[k] = *at_node<CT>(Pn, m);
         if (WALL) sGD[k] = (CT)(cs.grav[0] * off[0] + cs.grav[1] * off[1] + cs.grav[2] * off[2]);
+        if (WALL && (cr & kOpenGhost)) {
+            sP[k] = (CT)(2.0 * cs.p_top - (double)sP[k]);
+            sGD[k] = 0;
+        }
     }
     __syncthreads();
     int lx, ly, lz;
@@ -844,6 +942,12 @@ __device__ __forceinline__ void velocity_tile(CDesc& cs, const TileCtx& t, CT* s
     const int x = t.ox + lx, y = t.oy + ly, z = t.oz + lz;
     if (x >= cs.nx || y >= cs.ny || z >= cs.nz) return;
     const uint32_t n = (uint32_t)x + (uint32_t)cs.nx * ((uint32_t)y + (uint32_t)cs.ny * (uint32_t)z);
+    if (WALL && in_block(cs, x, y, z)) {
+        const Slots<CT> Us = slots<CT>(cs.U[t.step & 1], cs.N);
+#pragma unroll
+        for (int a = 0; a < DIMV; ++a) *Us.at(a, n * (uint32_t)sizeof(CT)) = 0;
+        return;
+    }
     const CT ra = (CT)cs.rho_a, dr = (CT)(cs.rho_w - cs.rho_a);
     const CT rho = ra + clamp01(*at_node<CT>(cs.phi[t.step & 1], n)) * dr;
     const CT irho = rcp(rho);
@@ -929,7 +1033,8 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
     int lx, ly, lz;
     local_xyz<Mo>(&lx, &ly, &lz);
     const int x = t.ox + lx, y = t.oy + ly, z = t.oz + lz;
-    const bool inside = x < cs.nx && y < cs.ny && z < cs.nz;
+    // block nodes carry no fluid and are skipped like nodes past the grid
+    const bool inside = x < cs.nx && y < cs.ny && z < cs.nz && !(WALL && in_block(cs, x, y, z));
     const uint32_t n = inside ? (uint32_t)x + (uint32_t)cs.nx * ((uint32_t)y + (uint32_t)cs.ny * (uint32_t)z) : 0u;
     const uint32_t nb = n * (uint32_t)sizeof(S), na = n * (uint32_t)sizeof(CT);
     const bool odd = t.step & 1;
@@ -964,7 +1069,7 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
         const int k = threadIdx.x + 256 * it;
         if (k >= R::N) break;
         int off[3], cr;
-        const uint32_t m = HR::cell(cs, t, k, off, &cr);
+        const uint32_t m = HR::template cell<WALL>(cs, t, k, off, &cr);
         const CT f = *at_node<CT>(cs.phi[t.step & 1], m);
         sPhi[k] = f;
         sRho[k] = ph.rho_a + clamp01(f) * ph.drho;
@@ -1050,6 +1155,7 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
             gk += omf * (ak - gk);
         }
         if (WALL) {
+            const bool oi = nav_open<G>(nv, i, +1), ok = nav_open<G>(nv, i + 1, +1);
             CT cF = 0;
 #pragma unroll
             for (int a = 0; a < DIMV; ++a) {
@@ -1058,8 +1164,16 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
             }
             // a reflected population keeps the force part of its equilibrium
             const CT fc = (CT)G::w(i) * cF * corr;
-            gi -= bi ? fc : (CT)0;
-            gk += bk ? fc : (CT)0;
+            gi -= (bi && !oi) ? fc : (CT)0;
+            gk += (bk && !ok) ? fc : (CT)0;
+            // through the open end: the population leaves, and the opposite
+            // one entering this node is the node's own equilibrium
+            if (oi || ok) {
+                CT ei, ek;
+                g_pair<G, DIMV, true>(v, kc, i, &ei, &ek);
+                if (oi) gi = ek;
+                if (ok) gk = ei;
+            }
         }
         aa_store<G, WALL, nt_access<S, kStoreCollide>()>(gs, nb, nv, i, odd, Codec<S>::enc(gi, gsc, gref_out(i, bi)),
                                                          bi);
@@ -1162,11 +1276,25 @@ __global__ __launch_bounds__(256) void k_init(CaseTab cases, const int* hdr,
     const int x = t.ox + lx, y = t.oy + ly, z = t.oz + lz;
     if (x >= cs.nx || y >= cs.ny || z >= cs.nz) return;
     const uint32_t n = (uint32_t)x + (uint32_t)cs.nx * ((uint32_t)y + (uint32_t)cs.ny * (uint32_t)z);
+    const Slots<S> hs = slots<S>(cs.h, cs.N), gs = slots<S>(cs.g, cs.N);
+    const uint32_t nb = n * (uint32_t)sizeof(S);
+    const Slots<CT> U1 = slots<CT>(cs.U[1], cs.N);
+    if (in_block(cs, x, y, z)) {
+        // block nodes hold no populations and no fluid
+#pragma unroll
+        for (int j = 0; j < H::Q; ++j) *hs.at(j, nb) = Codec<S>::enc((CT)0, (CT)1, (CT)0);
+#pragma unroll
+        for (int i = 0; i < G::Q; ++i) *gs.at(i, nb) = Codec<S>::enc((CT)0, (CT)1, (CT)0);
+        *at_node<CT>(cs.P[0], n) = 0;
+        *at_node<CT>(cs.P[1], n) = 0;
+        *at_node<CT>(cs.phi[1], n) = 0;
+#pragma unroll
+        for (int a = 0; a < DIMV; ++a) *U1.at(a, n * (uint32_t)sizeof(CT)) = 0;
+        return;
+    }
     NodeVals<CT> v;
     tile_gradients<LS, R, CT>(sPhi, sRho, sU, lx + 1, ly + 1, lz + HR::ZH, v);
     const NodeCoef<DIMV, CT> kc = node_coef<DIMV, true, CT>(ph, v, (const CT*)nullptr);
-    const Slots<S> hs = slots<S>(cs.h, cs.N), gs = slots<S>(cs.g, cs.N);
-    const uint32_t nb = n * (uint32_t)sizeof(S);
     const CT hsc = (CT)cs.h_scale, gsc = (CT)cs.g_scale;
     // 2-byte storage: h_j - w_j phi0 (the previous-step phi of step 0 is phi0)
     const CT phr = sizeof(S) == 2 ? v.phi : (CT)0;
@@ -1186,7 +1314,6 @@ __global__ __launch_bounds__(256) void k_init(CaseTab cases, const int* hdr,
                                       sizeof(S) == 2 ? g_ref<G, DIMV>(i, v.u) : (CT)0);
     *at_node<CT>(cs.P[0], n) = (CT)P0[n];
     *at_node<CT>(cs.phi[1], n) = v.phi;
-    const Slots<CT> U1 = slots<CT>(cs.U[1], cs.N);
 #pragma unroll
     for (int a = 0; a < DIMV; ++a) *U1.at(a, n * (uint32_t)sizeof(CT)) = v.u[a];
 }

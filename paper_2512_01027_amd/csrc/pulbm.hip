@@ -86,6 +86,13 @@ Layout make_layout(const pulbm_params& p)
     return L;
 }
 
+bool has_block(const pulbm_params& p)
+{
+    for (int a = 0; a < 3; ++a)
+        if (p.block_lo[a] >= p.block_hi[a]) return false;
+    return true;
+}
+
 int validate(const pulbm_params* p)
 {
     if (!p) return fail(PULBM_EINVAL, "params is NULL");
@@ -107,9 +114,27 @@ int validate(const pulbm_params* p)
                     nodes, widest);
     if (p->collision != 0 && p->collision != 1)
         return fail(PULBM_EINVAL, "collision must be 0 (filter) or 1 (BGK)");
-    for (int a = 0; a < 3; ++a)
-        if (p->wall[a] != 0 && p->wall[a] != 1) return fail(PULBM_EINVAL, "wall[%d] must be 0 or 1", a);
+    for (int a = 0; a < 3; ++a) {
+        if (p->wall[a] < 0 || p->wall[a] > 2) return fail(PULBM_EINVAL, "wall[%d] must be 0, 1 or 2", a);
+        if (p->wall[a] == 2 && a != p->dim - 1)
+            return fail(PULBM_EINVAL, "wall = 2 (open high end) is for the last axis only (axis %d)", p->dim - 1);
+    }
     if (p->dim == 2 && p->wall[2]) return fail(PULBM_EINVAL, "2D cases have no z walls");
+    if (!std::isfinite(p->p_top)) return fail(PULBM_EINVAL, "p_top must be finite");
+    if (has_block(*p)) {
+        const int n[3] = {p->nx, p->ny, p->nz};
+        for (int a = 0; a < 3; ++a) {
+            const int lo = p->block_lo[a], hi = p->block_hi[a];
+            const bool full = lo == 0 && hi == n[a];
+            if (lo < 0 || hi > n[a]) return fail(PULBM_EINVAL, "block exceeds the grid on axis %d", a);
+            if (!full && hi - lo < 2)
+                return fail(PULBM_EINVAL, "block must be at least 2 nodes thick on axis %d (or span it)", a);
+            if (!full && !p->wall[a] && (lo < 1 || hi > n[a] - 1))
+                return fail(PULBM_EINVAL, "block may not touch the periodic boundary of axis %d", a);
+            if (p->wall[a] == 2 && hi == n[a])
+                return fail(PULBM_EINVAL, "block may not touch the open end of axis %d", a);
+        }
+    }
     if (!(p->rho_heavy > 0) || !(p->rho_light > 0) || !(p->rho_heavy > p->rho_light))
         return fail(PULBM_EINVAL, "densities must satisfy rho_heavy > rho_light > 0");
     if (!(p->nu_heavy > 0) || !(p->nu_light > 0)) return fail(PULBM_EINVAL, "viscosities must be > 0");
@@ -331,6 +356,12 @@ extern "C" int pulbm_create(const pulbm_params* p, void* dev_arena, size_t arena
     h.tau_w = p->nu_heavy / kT + 0.5;
     h.tau_phi = p->M / kT + 0.5;
     h.M = p->M; h.W = p->W; h.sigma = p->sigma; h.lambda_b = p->lambda_bulk;
+    h.p_top = p->p_top;
+    h.has_block = has_block(*p);
+    for (int a = 0; a < 3; ++a) {
+        h.blk_lo[a] = h.has_block ? p->block_lo[a] : 0;
+        h.blk_hi[a] = h.has_block ? p->block_hi[a] : 0;
+    }
     codec_constants(*p, h);
     c->d = (CaseDev*)(c->base + L.desc);
     c->tab = (CaseDev**)(c->base + L.tab);

@@ -163,6 +163,72 @@ def config_dam_break_3d(nx=512, ny=256, nz=256, store="fp16"):
     return cfg, (phi, P, u), 20000
 
 
+# Dam break against a block (Sec. III): container 3.22 x 1 x 1 m at 5.5 mm
+# per node, water column H = 0.55 m high, block 0.161 x 0.403 x 0.161 m with
+# its near face 0.744 m from the left end, centred across; water 999.10 and
+# air 1.225 kg/m^3, nu 1.139e-6 and 1.461e-5 m^2/s, sigma 0.072 N/m; the
+# characteristic velocity sqrt(2 g H) is 0.0289 in lattice units.  Sensors
+# (centred across): water heights at 0.496, 0.992 and 2.638 m from the left
+# end; pressures on the block at heights 0.021 and 0.101 m on its face toward
+# the water and on its top 0.021 m from that face.
+DAM = {"L": 3.22, "B": 1.0, "Hbox": 1.0, "dx": 5.5e-3, "H": 0.55, "block": (0.161, 0.403, 0.161),
+       "block_x": 0.744, "rho_w": 999.10, "rho_a": 1.225, "nu_w": 1.139e-6, "nu_a": 1.461e-5,
+       "sigma": 0.072, "U": 0.0289, "heights": (0.496, 0.992, 2.638), "p_face": (0.021, 0.101),
+       "p_top_from_face": 0.021}
+
+
+def config_dam_break_block(store="fp16", nu_water=2e-3, column=0.25, q_hydro=27):
+    """The dam break against a block (MARIN geometry of Sec. III) in lattice
+    units: 585 x 182 x 182 nodes; walls on the sides and the floor, the top
+    open at P = 0; gravity from sqrt(2 g H) = 0.0289 with H = 100 nodes;
+    density ratio 815.6, air / water viscosity ratio 12.8 and sigma from the
+    physical values at the time step that velocity fixes.  The water's
+    physical viscosity would put tau within 1e-5 of 1/2, beyond what the
+    step is stable at, so nu_water is a parameter (2e-3: tau = 0.506).  The
+    paper does not give the water column's length: it is column x the
+    container length, at the end away from the block.
+    Returns cfg, fields and a dict of sensor positions (node indices)."""
+    d = DAM
+    dx = d["dx"]
+    nx, ny, nz = (int(round(v / dx)) for v in (d["L"], d["B"], d["Hbox"]))
+    H = int(round(d["H"] / dx))
+    g = d["U"] ** 2 / (2.0 * H)
+    dt = dx * d["U"] / math.sqrt(2.0 * 9.81 * d["H"])
+    sigma = d["sigma"] * dt * dt / (d["rho_a"] * dx ** 3)
+    bx, by, bz = (int(round(v / dx)) for v in d["block"])
+    x0 = int(round(d["block_x"] / dx))
+    y0 = (ny - by) // 2
+    cfg = base_case(3, nx, ny, nz, q_hydro=q_hydro, wall=(1, 1, 2), gravity=(0.0, 0.0, -g), p_top=0.0,
+                    rho_heavy=d["rho_w"] / d["rho_a"], rho_light=1.0, nu_heavy=nu_water,
+                    nu_light=nu_water * d["nu_a"] / d["nu_w"], sigma=sigma, W=4.0, store=store,
+                    block=((x0, y0, 0), (x0 + bx, y0 + by, bz)))
+    x, y, z = _grid(cfg)
+    xc = nx - int(round(column * nx))
+    dxw = x - (xc - 0.5)
+    dzw = (H - 0.5) - z
+    dist = np.minimum(dxw, dzw)
+    corner = (dxw < 0) & (dzw < 0)
+    dist = np.where(corner, -np.sqrt(dxw * dxw + dzw * dzw), dist)
+    phi = tanh_profile(dist, cfg["W"])
+    # hydrostatic pressure of the column, P = 0 above it (the open top's level)
+    rho = cfg["rho_light"] + phi * (cfg["rho_heavy"] - cfg["rho_light"])
+    P = np.zeros_like(phi)
+    P[nz - 1] = 0.5 * g * rho[nz - 1]
+    for k in range(nz - 2, -1, -1):
+        P[k] = P[k + 1] + 0.5 * g * (rho[k] + rho[k + 1])
+    u = np.zeros((3,) + phi.shape)
+    blk = (slice(0, bz), slice(y0, y0 + by), slice(x0, x0 + bx))
+    phi[blk] = 0.0
+    P[blk] = 0.0
+    face = x0 + bx  # first fluid node past the block's face toward the water
+    sensors = {"heights_x": [int(round(v / dx)) for v in d["heights"]], "y": ny // 2,
+               "P1": (face, ny // 2, int(round(d["p_face"][0] / dx))),
+               "P3": (face, ny // 2, int(round(d["p_face"][1] / dx))),
+               "P5": (face - 1 - int(round(d["p_top_from_face"] / dx)), ny // 2, bz),
+               "steps_per_second": 1.0 / dt, "g": g}
+    return cfg, (phi, P, u), sensors
+
+
 # Table I of Sec. III.D: surrounding fluid density, dynamic viscosities of
 # the surrounding fluid (1) and the bubble (2), surface tension.
 TABLE1 = {1: {"rho1": 2.2, "mu1": 7.3e-3, "mu2": 7.3e-4, "sigma": 3.0e-5},
@@ -193,14 +259,21 @@ def config_table1_bubble(case, store="fp64"):
 HEAD_ON = {"Re": 1715.0, "We": 58.4, "nu_air_over_water": 15.1}
 
 
-def config_head_on_collision(D=64.0, U=0.04, grid=(256, 192, 192), gap=8.0, store="fp32", q_hydro=19):
+def config_head_on_collision(D=64.0, U=0.06, grid=(256, 192, 192), gap=8.0, store="fp32", q_hydro=19,
+                             offset=(0.0, 0.0, 0.0)):
     """Two water droplets of diameter D (nodes) in air approaching along x
     with relative velocity U (lattice units), periodic box.  The lattice
     units keep the paper's Re, We and air / water viscosity ratio:
     nu_water = U D / Re, nu_air = 15.1 nu_water, sigma = rho_water U^2 D / We.
+    U D must keep nu_water near 2e-3 or above: at nu_water = 1.1e-3 the
+    collision diverges (on the CPU reference as on the GPU), at 2.2e-3 it
+    runs (U D = 3.84, the default D = 64, U = 0.06).
     D3Q19 for both lattices (the paper's 3D lattice) unless q_hydro = 27.
     Each droplet moves at U / 2 (weighted by its own phi) and holds the
     Laplace pressure 2 sigma / R; the droplets start gap nodes apart.
+    offset moves the pair off the grid's mirror planes (on them, grad phi
+    vanishes exactly at nodes where theta is not small, and the interface
+    normal follows rounding).
     Returns cfg, fields and the steps of one time unit D / U."""
     nx, ny, nz = grid
     h = HEAD_ON
@@ -209,12 +282,15 @@ def config_head_on_collision(D=64.0, U=0.04, grid=(256, 192, 192), gap=8.0, stor
                     nu_light=h["nu_air_over_water"] * nu_w, W=4.0, store=store)
     x, y, z = _grid(cfg)
     R = D / 2.0
-    c1 = nx / 2.0 - R - gap / 2.0
-    c2 = nx / 2.0 + R + gap / 2.0
-    rr = (y - ny / 2.0) ** 2 + (z - nz / 2.0) ** 2
+    c1 = nx / 2.0 - R - gap / 2.0 + offset[0]
+    c2 = nx / 2.0 + R + gap / 2.0 + offset[0]
+    rr = (y - ny / 2.0 - offset[1]) ** 2 + (z - nz / 2.0 - offset[2]) ** 2
     p1 = tanh_profile(R - np.sqrt((x - c1) ** 2 + rr), cfg["W"])
     p2 = tanh_profile(R - np.sqrt((x - c2) ** 2 + rr), cfg["W"])
-    phi = np.maximum(p1, p2)
+    # the sum, not the max: smooth across the gap (a kink there puts zeros of
+    # lap(phi) where the delta-theta switch is active); p1 + p2 < 1 since the
+    # profiles are logistic in 4 d / W and the droplets are gap apart
+    phi = p1 + p2
     P, u = _zero_fields(cfg)
     P += 2.0 * cfg["sigma"] / R * phi
     u[0] = 0.5 * U * (p1 - p2)

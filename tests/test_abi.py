@@ -168,3 +168,29 @@ def test_last_error_is_thread_local(lib):
     t.join()
     assert seen == [""]
     assert lib.pulbm_last_error().decode() == mine
+
+
+@pytest.mark.parametrize("change,msg", [
+    (dict(wall=(2, 0, 0)), "last axis"),                          # open end on x in 3D
+    (dict(block=((4, 4, 4), (5, 8, 8))), "2 nodes thick"),        # 1-node block
+    (dict(block=((0, 4, 4), (6, 8, 8))), "periodic"),             # across a periodic face
+    (dict(wall=(0, 0, 2), block=((4, 4, 10), (8, 8, 16))), "open end"),
+    (dict(block=((4, 4, 4), (8, 8, 20))), "exceeds"),
+    (dict(p_top=float("inf")), "p_top"),
+])
+def test_invalid_boundaries_rejected(lib, change, msg):
+    cfg = W.base_case(3, 16, 12, 16, **change)
+    rc, _ = _req(lib, B.make_params(cfg))
+    assert rc == B.EINVAL
+    err = lib.pulbm_last_error().decode()
+    assert err and msg in err
+
+
+def test_block_and_open_end_accepted(lib):
+    cfg = W.base_case(3, 16, 12, 16, wall=(1, 1, 2), block=((4, 3, 0), (8, 7, 5)), p_top=0.1)
+    rc, size = _req(lib, B.make_params(cfg))
+    assert rc == 0 and size > 0
+    # 2D: the open end is on y
+    cfg2 = W.base_case(2, 16, 12, wall=(1, 2, 0), block=((4, 0, 0), (8, 5, 1)))
+    rc, _ = _req(lib, B.make_params(cfg2))
+    assert rc == 0

@@ -1,0 +1,124 @@
+"""The solid block and the open top at fixed pressure (the dam-break
+geometry of Sec. III) on the GPU against the FP64 CPU reference: block
+nodes, bounce-back into the block, mirrored stencil values at its faces,
+edges and corners, the open end's pressure ghosts and equilibrium inflow,
+alone and together, in 2D and 3D, with both collisions and both 3D hydro
+lattices; FP64 within 1e-10, FP32 within 2e-5 (relative to each field's
+largest magnitude; P after removing its mean)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2512_01027_amd import binding as B
+from paper_2512_01027_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _fields(cfg, R, center, seed=6):
+    phi, P, u = W.droplet(cfg, R, center=center)
+    phi = np.clip(phi + W.random_smooth(cfg, seed, amp=0.02), 0, 1)
+    for a in range(cfg["dim"]):
+        u[a] += W.random_smooth(cfg, seed + 1 + a, amp=0.01)
+    P += W.random_smooth(cfg, seed + 9, amp=1e-3) + cfg.get("p_top", 0.0)
+    return phi, P, u
+
+
+def _compare(got, ref, tol, tag):
+    (pg, Pg, ug), (pr, Pr, ur) = got, ref
+    e_phi = np.abs(pg - pr).max()
+    e_P = np.abs((Pg - Pg.mean()) - (Pr - Pr.mean())).max() / max(np.abs(Pr - Pr.mean()).max(), 1e-12)
+    e_u = np.abs(ug - ur).max() / max(np.abs(ur).max(), 1e-12)
+    msg = f"{tag} phi {e_phi:.2e} P {e_P:.2e} u {e_u:.2e}"
+    print(msg, flush=True)
+    assert e_phi < tol and e_P < tol and e_u < tol, msg
+
+
+CASES = {
+    # block on the floor of a closed box, droplet falling beside it
+    "3d_block_closed": dict(dim=3, nx=37, ny=14, nz=18, wall=(1, 1, 1), gravity=(0.0, 0.0, -1e-5),
+                            block=((12, 4, 0), (20, 10, 6)), R=4.5, center=(25.3, 7.4, 9.6)),
+    # block floating in a periodic box (every face, edge and corner exposed)
+    "3d_block_periodic": dict(dim=3, nx=30, ny=20, nz=17, block=((9, 6, 5), (14, 12, 9)), R=4.0,
+                              center=(20.2, 9.7, 8.3)),
+    # open top above a periodic layer, no block
+    "3d_open_top": dict(dim=3, nx=33, ny=9, nz=20, wall=(0, 0, 2), gravity=(0.0, 0.0, -1e-5), p_top=0.05,
+                        R=4.0, center=(15.6, 4.4, 8.2)),
+    # the dam-break geometry: walls on the sides, open top, block on the floor
+    "3d_dam_geometry": dict(dim=3, nx=40, ny=16, nz=20, wall=(1, 1, 2), gravity=(0.0, 0.0, -1e-5), p_top=0.02,
+                            block=((8, 5, 0), (13, 11, 5)), R=5.0, center=(26.4, 8.3, 7.1)),
+    "2d_dam_geometry": dict(dim=2, nx=70, ny=33, wall=(1, 2, 0), gravity=(0.0, -1e-5, 0.0), p_top=0.01,
+                            block=((20, 0, 0), (27, 6, 1)), R=7.0, center=(45.3, 12.6, 0.0)),
+}
+
+
+def _case(name, **over):
+    kw = dict(CASES[name])
+    dim, nx, ny = kw.pop("dim"), kw.pop("nx"), kw.pop("ny")
+    nz = kw.pop("nz", 1)
+    R, center = kw.pop("R"), kw.pop("center")
+    kw = dict(dict(nu_heavy=0.05, nu_light=0.15, sigma=0.01), **kw)
+    kw.update(over)
+    cfg = W.base_case(dim, nx, ny, nz, **kw)
+    return cfg, _fields(cfg, R, center)
+
+
+def _run_pair(cfg, f, tol, tag):
+    g = B.Case(cfg)
+    g.init_fields(*f)
+    o = oracle.OracleCase(dict(cfg, store="fp64"))
+    o.init_fields(*f)
+    _compare(g.read_fields(), o.read_fields(), tol, tag + " step 0")
+    for s in (1, 6, 23):
+        g.step(s)
+        o.step(s)
+        _compare(g.read_fields(), o.read_fields(), tol, f"{tag} +{s}")
+    d = g.diagnostics()
+    assert d["nonfinite"] == 0
+    mtol = 1e-9 if cfg["store"] == "fp64" else 1e-6
+    assert abs(d["phi_sum"] - o.diagnostics()["phi_sum"]) < mtol * abs(o.diagnostics()["phi_sum"])
+
+
+@pytest.mark.parametrize("store,tol", [("fp64", 1e-10), ("fp32", 2e-5)])
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_boundaries_match_oracle(name, store, tol):
+    """FP32 runs with the delta-theta correction off: in the air next to the
+    block the noisy inputs hold phi ~ 5e-3, on the correction's ramp, where
+    the sign switch s = lap(phi) / (|lap(phi)| + 1e-10) follows FP32 rounding
+    of lap(phi) near its zeros and moves phi by 1e-3 within 20 steps (with it
+    off, FP32 stays at 3e-7 of the reference over the same run).  FP64 runs
+    with it on."""
+    cfg, f = _case(name, store=store, delta_theta=1 if store == "fp64" else 0)
+    _run_pair(cfg, f, tol, f"{name} {store}")
+
+
+@pytest.mark.parametrize("variant", ["bgk", "d3q19"])
+def test_dam_geometry_variants_match_oracle(variant):
+    over = dict(store="fp64")
+    if variant == "bgk":
+        over.update(collision="bgk", nu_heavy=0.1, nu_light=0.1)
+    else:
+        over.update(q_hydro=19)
+    cfg, f = _case("3d_dam_geometry", **over)
+    _run_pair(cfg, f, 1e-10, f"3d_dam_geometry {variant}")
+
+
+def test_block_nodes_read_back_zero_and_fp16_runs():
+    """FP16 storage with block and open top: block nodes read back zero, and
+    after 40 steps phi and u are within 2e-3 of the FP64 reference (delta
+    theta off, as for FP32 above)."""
+    cfg, f = _case("3d_dam_geometry", store="fp16", delta_theta=0)
+    g = B.Case(cfg)
+    g.init_fields(*f)
+    g.step(40)
+    phi, P, u = g.read_fields()
+    (lo, hi) = cfg["block"]
+    blk = (slice(lo[2], hi[2]), slice(lo[1], hi[1]), slice(lo[0], hi[0]))
+    assert np.all(phi[blk] == 0) and np.all(P[blk] == 0) and np.all(u[(slice(None),) + blk] == 0)
+    o = oracle.OracleCase(dict(cfg, store="fp64"))
+    o.init_fields(*f)
+    o.step(40)
+    ref = o.read_fields()
+    assert np.abs(phi - ref[0]).max() < 2e-3
+    assert np.abs(u - ref[2]).max() < 2e-3 * np.abs(ref[2]).max()
+    assert g.diagnostics()["nonfinite"] == 0

@@ -2,7 +2,8 @@
 
 - each case's result is bitwise the same alone (the single-case API), alone
   in a batch and in a mix of 2D and 3D cases of other sizes, step counts and
-  collision operators and hydrodynamic lattices,
+  collision operators and hydrodynamic lattices, and one with a block and an
+  open top,
   including a case admitted while the others are part-way through;
 - each case runs exactly its requested number of steps, whatever the advance
   granularity;
@@ -34,7 +35,10 @@ def _cases(store):
     h = W.base_case(3, 21, 13, 11, q_hydro=19, wall=(1, 0, 1), gravity=(0.0, 0.0, -1e-5), sigma=0.01,
                     nu_heavy=0.05, nu_light=0.15, store=store)
     fh = W.droplet(h, 4.0, center=(10.3, 6.6, 4.2), heavy_inside=False)
-    return [(a, fa, 37), (b, fb, 50), (c, fc, 23), (d, fd, 41), (e, fe, 29), (h, fh, 33)]
+    k = W.base_case(3, 26, 12, 14, wall=(1, 1, 2), gravity=(0.0, 0.0, -1e-5), block=((6, 3, 0), (10, 8, 4)),
+                    p_top=0.01, sigma=0.01, nu_heavy=0.05, nu_light=0.15, store=store)
+    fk = W.droplet(k, 3.5, center=(17.2, 6.3, 6.4))
+    return [(a, fa, 37), (b, fb, 50), (c, fc, 23), (d, fd, 41), (e, fe, 29), (h, fh, 33), (k, fk, 27)]
 
 
 def _alone(cfg, f, n):
@@ -55,10 +59,10 @@ def test_alone_equals_mix_bitwise(store):
     cases = _cases(store)
     ref = [_alone(cfg, f, n) for cfg, f, n in cases]
     bt = B.Batch(1 << 30, store=store, max_slots=8)
-    # the first three, the BGK case and the D3Q19 case start together; the
+    # the first three, the BGK, D3Q19 and block cases start together; the
     # fourth arrives after 16 steps
     slots = {}
-    for k in (0, 1, 2, 4, 5):
+    for k in (0, 1, 2, 4, 5, 6):
         cfg, f, n = cases[k]
         slots[bt.admit(cfg, *f, n)] = k
     got = {}
