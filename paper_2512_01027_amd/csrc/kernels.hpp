@@ -702,16 +702,11 @@ __device__ __forceinline__ CT c_dot(int j, const CT* u)
     return cu;
 }
 template <class CT> __device__ __forceinline__ CT g_shift(CT w, CT cu) { return (w * (CT)3) * cu; }
-#ifdef PULBM_SHIFT_FACE_EDGE
-template <class L> constexpr bool shifted_dir(int i) { return (L::c(i, 0) != 0) + (L::c(i, 1) != 0) + (L::c(i, 2) != 0) < 3; }
-#else
-template <class L> constexpr bool shifted_dir(int) { return true; }
-#endif
 // shift of an incoming g_i read by a node whose previous-step velocity is u
 template <class G, int D, class CT>
 __device__ __forceinline__ CT g_ref(int i, const CT* u)
 {
-    return shifted_dir<G>(i) ? g_shift((CT)G::w(i), c_dot<G, D>(i, u)) : (CT)0;
+    return g_shift((CT)G::w(i), c_dot<G, D>(i, u));
 }
 
 // previous-step velocity of node n in 2-byte storage (wider storage: zero, unread)
@@ -1107,10 +1102,10 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
             CT ud[3] = {0, 0, 0};
 #pragma unroll
             for (int a = 0; a < DIMV; ++a)
-                if (G::c(i, a) != 0 && shifted_dir<G>(i)) ud[a] = sU[a][k];
+                if (G::c(i, a) != 0) ud[a] = sU[a][k];
             CT cu = c_dot<G, DIMV>(i, ud);
             if (reflected) cu = -cu;
-            return shifted_dir<G>(i) ? g_shift((CT)G::w(i), cu) : (CT)0;
+            return g_shift((CT)G::w(i), cu);
         }
     };
     auto href_out = [&](int i, bool reflected) -> CT {
@@ -1140,6 +1135,10 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
     CT hmoved = 0;
 #pragma unroll
     for (int i = 1; i < G::Q; i += 2) {
+        // 2-byte storage: keep the scheduler from interleaving pairs (the
+        // codec shifts' LDS reads, hoisted across pairs, push the D3Q27
+        // kernel past its register budget into scratch spills)
+        if constexpr (sizeof(S) == 2) PULBM_PHASE_FENCE();
         const bool bi = WALL && nav_solid<G>(nv, i, +1);
         const bool bk = WALL && nav_solid<G>(nv, i + 1, +1);
         CT gi, gk;
