@@ -1,10 +1,16 @@
 """Long runs of the large 3D workloads at their real sizes (GPU only).
 
+    python -m paper_2512_01027_amd.longruns galilean [--out FILE]
     python -m paper_2512_01027_amd.longruns rising_bubble [--out FILE]
     python -m paper_2512_01027_amd.longruns dam_break [--out FILE]
     python -m paper_2512_01027_amd.longruns head_on [--out FILE]
     python -m paper_2512_01027_amd.longruns dam_block [--out FILE] [--store fp16|fp32] [--seconds T]
 
+galilean
+    The 128^3 droplet (R = 24) translated with u = (0.05, 0.02, 0) for 5000
+    steps in FP64 and FP32 storage: shape drift ||phi(5000) - phi0 moved by
+    (250, 100, 0)|| / ||phi0||, the centroid velocity error, and FP32
+    against FP64 (relative L2 of phi, u and the mean-subtracted P).
 rising_bubble
     The 256^3 rising bubble (walls in z, g = -1e-6 z, R = 32 at a quarter
     height) with FP32, FP16 and BF16 storage against the FP64 storage mode of
@@ -86,6 +92,28 @@ def _run(cfg, fields, marks, emit, tag, keep):
 def _errors(got, ref):
     (pg, Pg, ug), (pr, Pr, ur) = got, ref
     return {"phi": _rel(pg, pr), "u": _rel(ug, ur), "P": _rel(Pg - Pg.mean(), Pr - Pr.mean())}
+
+
+def galilean(emit, steps=5000, n=128):
+    from . import analysis as A
+
+    cfg, fields, _ = W.config_galilean_droplet_3d(n)
+    u0 = (0.05, 0.02, 0.0)
+    shift = tuple(int(round(v * steps)) for v in u0)
+    out = {}
+    for store in ("fp64", "fp32"):
+        out[store] = _run(dict(cfg, store=store), fields, [steps], emit, "galilean", lambda f: f)[0]
+        phi = out[store][0]
+        # move the droplet back by the distance the flow carries it
+        back = np.roll(phi, shift=(-shift[2], -shift[1], -shift[0]), axis=(0, 1, 2))
+        c0 = A.centroid(1.0 - np.clip(fields[0], 0, 1))
+        c1 = A.centroid(1.0 - np.clip(back, 0, 1))
+        emit({"run": "galilean", "store": store, "step": steps,
+              "shape_drift": float(f"{_rel(back, fields[0]):.3e}"),
+              "centroid_velocity_error": [float(f"{(b - a) / steps:.3e}") for a, b in zip(c0, c1)]})
+    emit({"run": "galilean", "compare": "fp32 vs fp64", "step": steps,
+          **{k: float(f"{v:.3e}") for k, v in _errors(out["fp32"], out["fp64"]).items()}})
+    return True
 
 
 def rising_bubble(emit, marks=(1000, 2000, 4000), n=256):
@@ -186,7 +214,7 @@ def dam_block(emit, store="fp16", seconds=2.0, every=0.1):
 
 def main(argv):
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=("rising_bubble", "dam_break", "head_on", "dam_block"))
+    ap.add_argument("which", choices=("galilean", "rising_bubble", "dam_break", "head_on", "dam_block"))
     ap.add_argument("--out", default=None)
     ap.add_argument("--store", default="fp16")
     ap.add_argument("--seconds", type=float, default=2.0)
@@ -195,7 +223,8 @@ def main(argv):
     if args.which == "dam_block":
         ok = dam_block(emit, args.store, args.seconds)
     else:
-        ok = {"rising_bubble": rising_bubble, "dam_break": dam_break, "head_on": head_on}[args.which](emit)
+        ok = {"galilean": galilean, "rising_bubble": rising_bubble, "dam_break": dam_break,
+              "head_on": head_on}[args.which](emit)
     return 0 if ok else 1
 
 
