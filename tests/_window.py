@@ -10,7 +10,10 @@ moment stage once more) a node therefore depends only on nodes within
 out of the initial fields, reproduces the node's values exactly: the window
 edge (periodic wrap of the window, or a wall where the window is cut inside
 a walled axis) lies outside the dependency cone.  Windows at a real wall keep
-that wall where it is.
+that wall where it is, windows reaching an open end keep it open, and the
+part of a solid block inside a window stays a block there (a sliver of it
+thinner than two nodes at a cut window edge is left out: it lies outside
+the cone).
 """
 from __future__ import annotations
 
@@ -37,7 +40,7 @@ def window_axes(cfg, center, half):
         elif walls[a]:
             lo, hi = max(0, c - half), min(n, c + half + 1)
             idx.append(np.arange(lo, hi))
-            wall.append(1)
+            wall.append(2 if walls[a] == 2 and hi == n else 1)
             pos.append(c - lo)
         else:
             idx.append(np.arange(c - half, c + half + 1) % n)
@@ -64,6 +67,20 @@ def window_reference(cfg, fields, center, steps, half=None):
     wP = P[sel]
     wu = np.stack([u[a][sel] for a in range(cfg["dim"])])
     wcfg = dict(cfg, nx=len(ix), ny=len(iy), nz=len(iz), wall=tuple(wall), store="fp64")
+    if cfg.get("block"):
+        blo, bhi = cfg["block"]
+        lo_w, hi_w = [], []
+        for a, arr in enumerate(idx):
+            if np.any(np.diff(arr) != 1):
+                raise ValueError("a block in a window that wraps a periodic axis")
+            lo_w.append(int(np.clip(blo[a] - arr[0], 0, len(arr))))
+            hi_w.append(int(np.clip(bhi[a] - arr[0], 0, len(arr))))
+        keep = all(h > l for l, h in zip(lo_w, hi_w))
+        for a, arr in enumerate(idx):
+            full = lo_w[a] == 0 and hi_w[a] == len(arr)
+            if not full and hi_w[a] - lo_w[a] < 2:
+                keep = False
+        wcfg["block"] = (tuple(lo_w), tuple(hi_w)) if keep else None
     o = oracle.OracleCase(wcfg)
     o.init_fields(wphi, wP, wu)
     o.step(steps)

@@ -39,8 +39,8 @@ def _run_gpu(cfg, f, steps):
     return out
 
 
-def _check(tag, cfg, f, steps, stores, nsamp, seed):
-    centers = sample_centers(cfg, f, nsamp, seed)
+def _check(tag, cfg, f, steps, stores, nsamp, seed, extra=()):
+    centers = sample_centers(cfg, f, nsamp, seed) + list(extra)
     refs = [window_reference(cfg, f, c, steps, cone(steps) + 2) for c in centers]
     # field scales from the compared blocks only: outside the dependency cone
     # the window's own edge makes its values meaningless
@@ -87,3 +87,16 @@ def test_rising_bubble_256_walls_z():
 def test_dam_break_512x256x256_all_walls():
     cfg, f, _ = W.config_dam_break_3d()
     _check("dam_break_512x256x256", cfg, f, 2, [("fp16", FP16), ("fp32", FP32)], 12, 13)
+
+
+def test_dam_break_block_585x182x182_open_top():
+    """The dam break against a block in the container of Sec. III: samples
+    also at the block's face, top edge and corner, next to the floor beside
+    it, and at the open top."""
+    cfg, f, _ = W.config_dam_break_block(store="fp16")
+    (bx0, by0, _), (bx1, by1, bz1) = cfg["block"]
+    nz = cfg["nz"]
+    extra = [(bx1, (by0 + by1) // 2, bz1 // 2), (bx1, by0 + 3, bz1), (bx0 - 1, by0 - 1, bz1),
+             (bx1 + 1, by1, 0), (300, 91, nz - 1), (450, 20, nz - 1), (438, 100, 99)]
+    _check("dam_break_block_585x182x182", cfg, f, 2, [("fp16", FP16), ("fp32", FP32)], 8, 14, extra)
+

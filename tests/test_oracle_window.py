@@ -56,3 +56,23 @@ def test_sample_centers_cover_walls_and_interface():
     assert len(cs) == 16
     assert any(z in (0, cfg["nz"] - 1) for _, _, z in cs)
     assert any(0.05 < f[0][z, y, x] < 0.95 for x, y, z in cs)
+
+
+def test_window_with_block_and_open_top():
+    """Windows cut out of a case with a block and an open top keep the part
+    of the block inside them and the open end when they reach it."""
+    cfg = W.base_case(3, 60, 40, 44, wall=(1, 1, 2), gravity=(0.0, 0.0, -1e-5), p_top=0.01, nu_heavy=0.05,
+                      nu_light=0.15, sigma=0.01, block=((20, 10, 0), (28, 30, 9)))
+    phi, P, u = W.droplet(cfg, 6.0, center=(35.3, 20.2, 12.4))
+    phi[0:9, 10:30, 20:28] = 0.0
+    P[0:9, 10:30, 20:28] = 0.0
+    o = oracle.OracleCase(cfg)
+    o.init_fields(phi, P, u)
+    o.step(2)
+    full = o.read_fields()
+    # block face, top edge, corner, floor beside it, open top
+    for c in [(28, 20, 4), (27, 29, 9), (19, 9, 9), (21, 12, 0), (40, 20, 43)]:
+        ref, axes, pos = window_reference(cfg, (phi, P, u), c, 2)
+        got, want = inner_block(full, ref, axes, pos, 2)
+        for a, b in zip(got, want):
+            assert np.abs(a - b).max() <= 1e-13 * max(np.abs(b).max(), 1e-300), c
