@@ -20,8 +20,9 @@ Printed as one JSON line:
                  too (the lattice of the paper's 3D runs), FP32 and FP16
   workloads      throughput at the real sizes of the 3D rising bubble (256^3,
                  walls in z; FP32, FP16 and BF16 storage), the dam break
-                 (512 x 256 x 256, walls on all faces; FP16 and FP32) and the
+                 (512 x 256 x 256, walls on all faces; FP16 and FP32), the
                  dam break against a block with an open top (585 x 182 x 182)
+                 and the head-on droplet collision (256 x 192 x 192, D3Q19)
   serving        a seeded Poisson stream of droplet / bubble requests served
                  by continuous batching, p50 / p99 latency and aggregate MLUPS,
                  beside the same stream run one case at a time
@@ -207,7 +208,8 @@ def workloads_leg(steps=100, warmup=10):
 
     runs = [("rising_bubble_256cube", lambda st: W.config_rising_bubble_3d(256, store=st), ("fp32", "fp16", "bf16")),
             ("dam_break_512x256x256", lambda st: W.config_dam_break_3d(store=st), ("fp16", "fp32")),
-            ("dam_break_block_585x182x182", lambda st: W.config_dam_break_block(store=st), ("fp16", "fp32"))]
+            ("dam_break_block_585x182x182", lambda st: W.config_dam_break_block(store=st), ("fp16", "fp32")),
+            ("head_on_collision_256x192x192", lambda st: W.config_head_on_collision(store=st), ("fp32", "fp16"))]
     out = {}
     for name, make, stores in runs:
         leg = {}
@@ -217,10 +219,11 @@ def workloads_leg(steps=100, warmup=10):
             sb = {"fp32": 4, "fp16": 2, "bf16": 2}[st]
             dt, ms, dg = run_gpu(dict(cfg, store=st), fields, steps, warmup)
             m = n * steps / dt / 1e6
-            eff = m * 1e6 * state_bytes(sb) / 1e9
+            pops = cfg["q_hydro"] + cfg["q_phase"]
+            eff = m * 1e6 * state_bytes(sb, pops=pops) / 1e9
             leg[st] = {"MLUPS": round(m, 1), "effective_GBs": round(eff, 1),
                        "effective_frac_of_peak": round(eff / HBM_PEAK_GBS, 4),
-                       "collide_GBs": round(kernel_bytes(sb)["collide"] * n / (ms[3] * 1e-3) / 1e9, 1),
+                       "collide_GBs": round(kernel_bytes(sb, pops=pops)["collide"] * n / (ms[3] * 1e-3) / 1e9, 1),
                        "kernel_ms": {k: round(float(v), 4) for k, v in zip(KERNELS, ms)},
                        "nonfinite": dg["nonfinite"]}
         leg["nodes"] = n
