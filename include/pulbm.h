@@ -55,8 +55,11 @@ extern "C" {
 
 /* Case parameters, lattice units (Sec. II; defaults of Sec. III in brackets). */
 typedef struct {
-    int32_t dim, nx, ny, nz;     /* dim 2 (nz = 1) or 3; every n >= 1; nx*ny*nz below 2^28
-                                    nodes in FP64 storage, below 2^29 otherwise             */
+    int32_t dim, nx, ny, nz;     /* dim 2 (nz = 1) or 3; every n >= 1.  Device fields pad
+                                    each row to a multiple of 32 nodes; the padded count
+                                    (nx rounded up to 32) * ny * nz must stay below 2^28 in
+                                    FP64 storage, below 2^29 otherwise.  Host arrays are
+                                    compact (x fastest, no padding).                        */
     int32_t q_hydro, q_phase;    /* 2D: 9, 9; 3D: 27 or 19, 19 (hydro D3Q27, or D3Q19 as the
                                     paper's 3D runs; phase field D3Q19)                      */
     int32_t wall[3];             /* per axis: 0 periodic, 1 no-slip walls at both ends, 2

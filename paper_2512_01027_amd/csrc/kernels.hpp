@@ -47,8 +47,9 @@ struct CaseDev {
     int32_t wall[3];
     int32_t ntx, nty, ntz;  // tiles per axis
     int32_t delta_theta;
-    int32_t pad0;
-    int64_t N;
+    int32_t sx;        // row pitch in nodes: nx rounded up to 32, so that every row of a
+                       // tile starts on a 128-byte line (node n = x + sx (y + ny z))
+    int64_t N;         // nodes per field including the row padding (sx ny nz)
     int64_t step;      // steps done
     int64_t step_end;  // the case is advanced while step < step_end
     void* h;           // Q_h * N populations (storage type)
@@ -199,7 +200,7 @@ __device__ __forceinline__ Nav make_nav(CDesc& cs, int x, int y, int z, int esz)
     Nav v;
     const int p[3] = {x, y, z};
     const int n[3] = {cs.nx, cs.ny, cs.nz};
-    const int st[3] = {esz, esz * cs.nx, esz * cs.nx * cs.ny};
+    const int st[3] = {esz, esz * cs.sx, esz * cs.sx * cs.ny};
     v.solid = 0;
     v.open = 0;
 #pragma unroll
@@ -379,7 +380,7 @@ struct Halo1 {
                 }
             }
         }
-        return (uint32_t)m[0] + (uint32_t)cs.nx * ((uint32_t)m[1] + (uint32_t)cs.ny * (uint32_t)m[2]);
+        return (uint32_t)m[0] + (uint32_t)cs.sx * ((uint32_t)m[1] + (uint32_t)cs.ny * (uint32_t)m[2]);
     }
 };
 
@@ -731,7 +732,7 @@ __device__ __forceinline__ void moments_node(CDesc& cs, int x, int y, int z, boo
     using G = typename Mo::G;
     using H = typename Mo::H;
     using CT = typename Codec<S>::CT;
-    const uint32_t n = (uint32_t)x + (uint32_t)cs.nx * ((uint32_t)y + (uint32_t)cs.ny * (uint32_t)z);
+    const uint32_t n = (uint32_t)x + (uint32_t)cs.sx * ((uint32_t)y + (uint32_t)cs.ny * (uint32_t)z);
     const uint32_t nb = n * (uint32_t)sizeof(S);
     const Nav nv = make_nav(cs, x, y, z, (int)sizeof(S));
     const Slots<S> hs = slots<S>(cs.h, cs.N), gs = slots<S>(cs.g, cs.N);
@@ -803,7 +804,7 @@ __global__ __launch_bounds__(256) void k_moments(CaseTab cases, const int* hdr, 
             // block nodes carry no fluid: phi, u*, P*, M2 = 0
             using CT = typename Codec<S>::CT;
             constexpr int DIMV = Model<LS>::DIM;
-            const uint32_t n = (uint32_t)x + (uint32_t)cs.nx * ((uint32_t)y + (uint32_t)cs.ny * (uint32_t)z);
+            const uint32_t n = (uint32_t)x + (uint32_t)cs.sx * ((uint32_t)y + (uint32_t)cs.ny * (uint32_t)z);
             const uint32_t na = n * (uint32_t)sizeof(CT);
             *at_node<CT>(cs.phi[odd ? 1 : 0], n) = 0;
             *at_node<CT>(cs.Ps, n) = 0;
@@ -863,7 +864,7 @@ __device__ __forceinline__ void pressure_tile(CDesc& cs, const TileCtx& t, AT* s
     local_xyz<Mo>(&lx, &ly, &lz);
     const int x = t.ox + lx, y = t.oy + ly, z = t.oz + lz;
     if (x >= cs.nx || y >= cs.ny || z >= cs.nz) return;
-    const uint32_t n = (uint32_t)x + (uint32_t)cs.nx * ((uint32_t)y + (uint32_t)cs.ny * (uint32_t)z);
+    const uint32_t n = (uint32_t)x + (uint32_t)cs.sx * ((uint32_t)y + (uint32_t)cs.ny * (uint32_t)z);
     if (WALL && in_block(cs, x, y, z)) {
         *at_node<AT>(cs.P[(t.step + 1) & 1], n) = 0;
         return;
@@ -936,7 +937,7 @@ __device__ __forceinline__ void velocity_tile(CDesc& cs, const TileCtx& t, CT* s
     local_xyz<Mo>(&lx, &ly, &lz);
     const int x = t.ox + lx, y = t.oy + ly, z = t.oz + lz;
     if (x >= cs.nx || y >= cs.ny || z >= cs.nz) return;
-    const uint32_t n = (uint32_t)x + (uint32_t)cs.nx * ((uint32_t)y + (uint32_t)cs.ny * (uint32_t)z);
+    const uint32_t n = (uint32_t)x + (uint32_t)cs.sx * ((uint32_t)y + (uint32_t)cs.ny * (uint32_t)z);
     if (WALL && in_block(cs, x, y, z)) {
         const Slots<CT> Us = slots<CT>(cs.U[t.step & 1], cs.N);
 #pragma unroll
@@ -1030,7 +1031,7 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
     const int x = t.ox + lx, y = t.oy + ly, z = t.oz + lz;
     // block nodes carry no fluid and are skipped like nodes past the grid
     const bool inside = x < cs.nx && y < cs.ny && z < cs.nz && !(WALL && in_block(cs, x, y, z));
-    const uint32_t n = inside ? (uint32_t)x + (uint32_t)cs.nx * ((uint32_t)y + (uint32_t)cs.ny * (uint32_t)z) : 0u;
+    const uint32_t n = inside ? (uint32_t)x + (uint32_t)cs.sx * ((uint32_t)y + (uint32_t)cs.ny * (uint32_t)z) : 0u;
     const uint32_t nb = n * (uint32_t)sizeof(S), na = n * (uint32_t)sizeof(CT);
     const bool odd = t.step & 1;
     const Nav nv = make_nav(cs, inside ? x : 0, inside ? y : 0, inside ? z : 0, (int)sizeof(S));
@@ -1274,7 +1275,7 @@ __global__ __launch_bounds__(256) void k_init(CaseTab cases, const int* hdr,
     local_xyz<Mo>(&lx, &ly, &lz);
     const int x = t.ox + lx, y = t.oy + ly, z = t.oz + lz;
     if (x >= cs.nx || y >= cs.ny || z >= cs.nz) return;
-    const uint32_t n = (uint32_t)x + (uint32_t)cs.nx * ((uint32_t)y + (uint32_t)cs.ny * (uint32_t)z);
+    const uint32_t n = (uint32_t)x + (uint32_t)cs.sx * ((uint32_t)y + (uint32_t)cs.ny * (uint32_t)z);
     const Slots<S> hs = slots<S>(cs.h, cs.N), gs = slots<S>(cs.g, cs.N);
     const uint32_t nb = n * (uint32_t)sizeof(S);
     const Slots<CT> U1 = slots<CT>(cs.U[1], cs.N);
@@ -1355,6 +1356,7 @@ __global__ __launch_bounds__(256) void k_diag(const CaseDev* __restrict__ csp, d
     const AT* U = (const AT*)cs.U[cs.step & 1];
     double acc[kDiagVals] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < N; n += (int64_t)gridDim.x * 256) {
+        if (n % cs.sx >= cs.nx) continue;  // row padding
         const double f = (double)phi[n];
         const double pc = f < 0.0 ? 0.0 : (f > 1.0 ? 1.0 : f);
         const double rho = cs.rho_a + pc * (cs.rho_w - cs.rho_a);

@@ -59,9 +59,13 @@ struct Layout {
     size_t h, g, P0, P1, phi0, phi1, J, Ps, M2, U0, U1, desc, tab, partial, diag, total;
 };
 
+// Row pitch of every field: nx rounded up to 32 nodes, so that a tile row
+// (32 nodes in 3D, 64 in 2D) starts on a 128-byte line whatever nx is.
+int row_pitch(int nx) { return (nx + 31) & ~31; }
+
 Layout make_layout(const pulbm_params& p)
 {
-    const size_t N = (size_t)p.nx * p.ny * p.nz;
+    const size_t N = (size_t)row_pitch(p.nx) * p.ny * p.nz;
     const size_t sb = store_bytes(p.store), ab = aux_bytes(p.store);
     const int dim = p.dim, nm = dim == 2 ? 3 : 6;
     Layout L;
@@ -107,7 +111,7 @@ int validate(const pulbm_params* p)
     if (p->store < PULBM_STORE_FP64 || p->store > PULBM_STORE_BF16) return fail(PULBM_EINVAL, "bad store %d", p->store);
     // kernels address one field with 32-bit byte offsets (signed for the
     // periodic neighbour steps): N times the widest element must stay below 2^31
-    const double nodes = (double)p->nx * p->ny * p->nz;
+    const double nodes = (double)row_pitch(p->nx) * p->ny * p->nz;
     const int widest = std::max(store_bytes(p->store), aux_bytes(p->store));
     if (nodes * widest >= 2147483648.0)
         return fail(PULBM_EINVAL, "grid too large: %.0f nodes x %d bytes per field element must stay below 2^31",
@@ -278,15 +282,19 @@ void to_double(const std::vector<char>& raw, double* out, size_t n)
     for (size_t i = 0; i < n; ++i) out[i] = (double)src[i];
 }
 
-int fetch(pulbm_case* c, const void* dev, double* out, size_t n)
+// Copy `comps` fields (each of N padded nodes) from the device into compact
+// host rows of nx doubles.
+int fetch(pulbm_case* c, const void* dev, double* out, int comps)
 {
     if (!out) return PULBM_OK;
     const size_t ab = aux_bytes(c->p.store);
-    std::vector<char> raw(n * ab);
-    HIPC(hipMemcpyAsync(raw.data(), dev, n * ab, hipMemcpyDeviceToHost, c->stream));
+    const size_t nx = (size_t)c->p.nx, rows = (size_t)comps * c->p.ny * c->p.nz;
+    std::vector<char> raw(rows * nx * ab);
+    HIPC(hipMemcpy2DAsync(raw.data(), nx * ab, dev, (size_t)c->h.sx * ab, nx * ab, rows, hipMemcpyDeviceToHost,
+                          c->stream));
     HIPC(hipStreamSynchronize(c->stream));
-    if (ab == 8) to_double<double>(raw, out, n);
-    else to_double<float>(raw, out, n);
+    if (ab == 8) to_double<double>(raw, out, rows * nx);
+    else to_double<float>(raw, out, rows * nx);
     return PULBM_OK;
 }
 
@@ -343,7 +351,8 @@ extern "C" int pulbm_create(const pulbm_params* p, void* dev_arena, size_t arena
     else tiles_of<3>(*p, &h.ntx, &h.nty, &h.ntz);
     c->ntiles = h.ntx * h.nty * h.ntz;
     h.delta_theta = p->delta_theta;
-    h.N = (int64_t)p->nx * p->ny * p->nz;
+    h.sx = row_pitch(p->nx);
+    h.N = (int64_t)h.sx * p->ny * p->nz;
     h.step = 0;
     h.step_end = INT64_MAX;
     h.h = c->base + L.h; h.g = c->base + L.g;
@@ -390,12 +399,13 @@ extern "C" void pulbm_destroy(pulbm_case* c)
 extern "C" int pulbm_init_fields(pulbm_case* c, const double* phi, const double* P, const double* u)
 {
     if (!c || !phi || !P || !u) return fail(PULBM_EINVAL, "NULL argument");
-    const size_t N = (size_t)c->h.N;
+    const size_t N = (size_t)c->h.N;  // padded
+    const size_t nx = (size_t)c->p.nx, rows = (size_t)c->p.ny * c->p.nz, Nc = nx * rows;
     const int dim = c->p.dim;
-    for (size_t n = 0; n < N; ++n)
+    for (size_t n = 0; n < Nc; ++n)
         if (!std::isfinite(phi[n]) || !std::isfinite(P[n]))
             return fail(PULBM_EDIVERGED, "non-finite initial phi or P at node %zu", n);
-    for (size_t n = 0; n < (size_t)dim * N; ++n)
+    for (size_t n = 0; n < (size_t)dim * Nc; ++n)
         if (!std::isfinite(u[n])) return fail(PULBM_EDIVERGED, "non-finite initial u at entry %zu", n);
     c->h.step = 0;
     c->h.step_end = INT64_MAX;
@@ -411,10 +421,12 @@ extern "C" int pulbm_init_fields(pulbm_case* c, const double* phi, const double*
         HIPC(hipMalloc((void**)&tmp, bytes));
         own_tmp = true;
     }
-    hipError_t e = hipMemcpyAsync(tmp, phi, N * sizeof(double), hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(tmp + N, P, N * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    // compact host rows of nx into device rows of sx (the padding is never read)
+    const size_t dp = (size_t)c->h.sx * sizeof(double), hp = nx * sizeof(double);
+    hipError_t e = hipMemcpy2DAsync(tmp, dp, phi, hp, hp, rows, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpy2DAsync(tmp + N, dp, P, hp, hp, rows, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(tmp + 2 * N, u, (size_t)dim * N * sizeof(double), hipMemcpyHostToDevice, c->stream);
+        e = hipMemcpy2DAsync(tmp + 2 * N, dp, u, hp, hp, (size_t)dim * rows, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) {
         launch_init(lattice_set(dim, c->p.q_hydro), c->p.store, c->stream, c->tab, c->hdr, grid_of(c->ntiles), tmp, tmp + N, tmp + 2 * N);
         e = hipGetLastError();
@@ -499,10 +511,9 @@ extern "C" int pulbm_read_fields(pulbm_case* c, double* phi, double* P, double* 
     if (!c->ready) return fail(PULBM_ESTATE, "read before init");
     int rc = read_pass(c);
     if (rc) return rc;
-    const size_t N = (size_t)c->h.N;
-    if ((rc = fetch(c, c->h.phi[c->step & 1], phi, N))) return rc;
-    if ((rc = fetch(c, c->h.P[(c->step + 1) & 1], P, N))) return rc;
-    if ((rc = fetch(c, c->h.U[c->step & 1], u, (size_t)c->p.dim * N))) return rc;
+    if ((rc = fetch(c, c->h.phi[c->step & 1], phi, 1))) return rc;
+    if ((rc = fetch(c, c->h.P[(c->step + 1) & 1], P, 1))) return rc;
+    if ((rc = fetch(c, c->h.U[c->step & 1], u, c->p.dim))) return rc;
     return PULBM_OK;
 }
 
@@ -536,8 +547,8 @@ extern "C" int pulbm_diagnostics(pulbm_case* c, pulbm_diag* d)
 // Restart image: header, h, g, previous-step pressure, previous-step phi and
 // u (the references of the 2-byte codecs).
 namespace {
-constexpr char kCkptMagic[9] = "PULBMCK3";
-constexpr int32_t kCkptVersion = 3;
+constexpr char kCkptMagic[9] = "PULBMCK4";
+constexpr int32_t kCkptVersion = 4;
 struct CkptHeader {
     char magic[8];
     int32_t version, store;
