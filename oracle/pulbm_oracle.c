@@ -11,7 +11,7 @@
  * particular K_i, the omega term and Pi are evaluated exactly as written (no
  * compact form), and streaming is a plain push into a second buffer.
  *
- * Readings of points the paper leaves open (each is also listed in the design doc):
+ * Readings of points the paper leaves open:
  *  R1  one LKS pass with no iteration, in the order the paper writes the two
  *      formulas.  The pressure equation holds P on both sides (through K_i);
  *      its one evaluation starts from the pressure the streamed populations

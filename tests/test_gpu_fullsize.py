@@ -25,7 +25,9 @@ from _window import cone, inner_block, ref_block, sample_centers, window_referen
 pytestmark = pytest.mark.gpu
 
 T_LATTICE = 1.0 / 3.0
-OUT = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+# per-case records of the GPU runs (one JSON line each)
+OUT = os.environ.get("PULBM_RESULTS_DIR",
+                     os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "results"))
 
 
 def _run_gpu(cfg, f, steps):

@@ -25,7 +25,9 @@ from paper_2512_01027_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-OUT = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+# per-case records of the GPU runs (one JSON line each)
+OUT = os.environ.get("PULBM_RESULTS_DIR",
+                     os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "results"))
 # off the grid's mirror planes, where the interface normal of an exactly
 # vanishing gradient would follow rounding
 SMALL = dict(D=32.0, U=0.12, grid=(96, 64, 64), offset=(0.37, 0.29, 0.61))

@@ -21,7 +21,9 @@ from paper_2512_01027_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-OUT = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+# per-case records of the GPU runs (one JSON line each)
+OUT = os.environ.get("PULBM_RESULTS_DIR",
+                     os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "results"))
 
 
 @pytest.mark.parametrize("case", [1, 2])
