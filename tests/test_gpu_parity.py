@@ -165,9 +165,14 @@ def test_fp32_matches_oracle(store, tol, case):
     _compare(g.read_fields(), o.read_fields(), tol, f"{case} {store}")
 
 
+@pytest.mark.parametrize("geometry", ["walls_z", "block_open_top"])
 @pytest.mark.parametrize("store", ["fp32", "fp16"])
-def test_checkpoint_restart_bitwise(store):
-    cfg = W.base_case(3, 21, 9, 10, wall=(0, 0, 1), gravity=(0, 0, -1e-5), store=store)
+def test_checkpoint_restart_bitwise(store, geometry):
+    if geometry == "walls_z":
+        cfg = W.base_case(3, 21, 9, 10, wall=(0, 0, 1), gravity=(0, 0, -1e-5), store=store)
+    else:
+        cfg = W.base_case(3, 37, 12, 14, wall=(1, 1, 2), gravity=(0, 0, -1e-5), p_top=0.01,
+                          block=((10, 3, 0), (16, 9, 5)), store=store)
     f = _fields(cfg)
     a = B.Case(cfg)
     a.init_fields(*f)
