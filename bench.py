@@ -141,6 +141,8 @@ def serving_leg(n_cases=64, step_scale=0.1):
     pois_b = SV.run_batched(reqs, budget)
     SV.set_arrivals(reqs, rate)
     pois_s = SV.run_sequential(reqs)
+    SV.set_arrivals(reqs, rate)
+    pois_sjf = SV.run_batched(reqs, budget, policy="sjf")
     # the same request mix restricted to small cases (at most 64^3 / 256^2
     # nodes), each far from filling the GPU on its own
     small = SV.make_stream(n_cases, "fp16", step_scale, case_seed=4, max_nodes=64 ** 3)
@@ -149,6 +151,7 @@ def serving_leg(n_cases=64, step_scale=0.1):
     SV.set_arrivals(small, None)
     small_s = SV.run_sequential(small)
     return {"saturated": SV.compare(burst_b, burst_s), "poisson": SV.compare(pois_b, pois_s),
+            "poisson_least_work_first": SV.compare(pois_sjf, pois_s),
             "small_cases_saturated": SV.compare(small_b, small_s),
             "sample": (f"{n_cases} requests (seed 3): 75% 3D n in [32,192], 25% 2D n in [128,1024] "
                        f"(log-uniform), droplet / rising bubble, density ratio 10/100/1000, "

@@ -275,26 +275,28 @@ int read_pass(pulbm_case* c)
     return PULBM_OK;
 }
 
+// Padded device rows of sx values -> compact host rows of nx doubles.
 template <class AT>
-void to_double(const std::vector<char>& raw, double* out, size_t n)
+void to_double(const std::vector<char>& raw, double* out, size_t rows, size_t nx, size_t sx)
 {
     const AT* src = (const AT*)raw.data();
-    for (size_t i = 0; i < n; ++i) out[i] = (double)src[i];
+    for (size_t r = 0; r < rows; ++r)
+        for (size_t i = 0; i < nx; ++i) out[r * nx + i] = (double)src[r * sx + i];
 }
 
 // Copy `comps` fields (each of N padded nodes) from the device into compact
-// host rows of nx doubles.
+// host rows of nx doubles: one contiguous copy (a strided copy to pageable
+// memory goes row by row), then the rows are compacted on the host.
 int fetch(pulbm_case* c, const void* dev, double* out, int comps)
 {
     if (!out) return PULBM_OK;
     const size_t ab = aux_bytes(c->p.store);
-    const size_t nx = (size_t)c->p.nx, rows = (size_t)comps * c->p.ny * c->p.nz;
-    std::vector<char> raw(rows * nx * ab);
-    HIPC(hipMemcpy2DAsync(raw.data(), nx * ab, dev, (size_t)c->h.sx * ab, nx * ab, rows, hipMemcpyDeviceToHost,
-                          c->stream));
+    const size_t nx = (size_t)c->p.nx, sx = (size_t)c->h.sx, rows = (size_t)comps * c->p.ny * c->p.nz;
+    std::vector<char> raw(rows * sx * ab);
+    HIPC(hipMemcpyAsync(raw.data(), dev, raw.size(), hipMemcpyDeviceToHost, c->stream));
     HIPC(hipStreamSynchronize(c->stream));
-    if (ab == 8) to_double<double>(raw, out, rows * nx);
-    else to_double<float>(raw, out, rows * nx);
+    if (ab == 8) to_double<double>(raw, out, rows, nx, sx);
+    else to_double<float>(raw, out, rows, nx, sx);
     return PULBM_OK;
 }
 
@@ -421,12 +423,17 @@ extern "C" int pulbm_init_fields(pulbm_case* c, const double* phi, const double*
         HIPC(hipMalloc((void**)&tmp, bytes));
         own_tmp = true;
     }
-    // compact host rows of nx into device rows of sx (the padding is never read)
-    const size_t dp = (size_t)c->h.sx * sizeof(double), hp = nx * sizeof(double);
-    hipError_t e = hipMemcpy2DAsync(tmp, dp, phi, hp, hp, rows, hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess) e = hipMemcpy2DAsync(tmp + N, dp, P, hp, hp, rows, hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess)
-        e = hipMemcpy2DAsync(tmp + 2 * N, dp, u, hp, hp, (size_t)dim * rows, hipMemcpyHostToDevice, c->stream);
+    // compact host rows of nx padded to rows of sx on the host (the padding is
+    // never read), then one contiguous copy
+    const size_t sx = (size_t)c->h.sx;
+    std::vector<double> staged((2 + (size_t)dim) * N, 0.0);
+    auto pad = [&](const double* src, double* dst, size_t nrows) {
+        for (size_t r = 0; r < nrows; ++r) std::memcpy(dst + r * sx, src + r * nx, nx * sizeof(double));
+    };
+    pad(phi, staged.data(), rows);
+    pad(P, staged.data() + N, rows);
+    pad(u, staged.data() + 2 * N, (size_t)dim * rows);
+    hipError_t e = hipMemcpyAsync(tmp, staged.data(), bytes, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) {
         launch_init(lattice_set(dim, c->p.q_hydro), c->p.store, c->stream, c->tab, c->hdr, grid_of(c->ntiles), tmp, tmp + N, tmp + 2 * N);
         e = hipGetLastError();

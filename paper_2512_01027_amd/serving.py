@@ -78,14 +78,17 @@ def _summary(reqs, makespan):
 
 
 def run_batched(reqs, hbm_budget: int, store: str = "fp16", k: int = 50, max_slots: int = 64,
-                fill_nodes: int = 12 << 20, admit_per_round: int = 4):
+                fill_nodes: int = 12 << 20, admit_per_round: int = 4, policy: str = "fifo"):
     """Continuous batching.  Returns the summary; sets each request's done.
 
-    Requests are admitted in arrival order, a few per round so that the GPU
-    starts on the first ones while later ones are set up, and only while the
-    resident cases hold fewer than fill_nodes nodes (enough to fill the GPU:
-    more would only share it among more cases and lengthen every latency).
+    Waiting requests are admitted in arrival order ("fifo") or least work
+    (nodes x steps) first ("sjf"), a few per round so that the GPU starts on
+    the first ones while later ones are set up, and only while the resident
+    cases hold fewer than fill_nodes nodes (enough to fill the GPU: more would
+    only share it among more cases and lengthen every latency).
     """
+    if policy not in ("fifo", "sjf"):
+        raise ValueError(f"unknown admission policy {policy!r}")
     bt = B.Batch(hbm_budget, store=store, max_slots=max_slots)
     pending = sorted(reqs, key=lambda r: r.arrival)
     waiting: list[Request] = []
@@ -99,6 +102,8 @@ def run_batched(reqs, hbm_budget: int, store: str = "fp16", k: int = 50, max_slo
         while i < len(pending) and pending[i].arrival <= now:
             waiting.append(pending[i])
             i += 1
+        if policy == "sjf":
+            waiting.sort(key=lambda r: (r.work, r.arrival))
         admitted = 0
         while waiting and admitted < admit_per_round:
             held = sum(r.nodes for r in resident.values())
@@ -125,7 +130,7 @@ def run_batched(reqs, hbm_budget: int, store: str = "fp16", k: int = 50, max_slo
     makespan = max(r.done for r in reqs) - min(r.arrival for r in reqs)
     bt.close()
     out = _summary(reqs, makespan)
-    out.update({"peak_resident": peak, "advance_steps": k, "fill_nodes": fill_nodes})
+    out.update({"peak_resident": peak, "advance_steps": k, "fill_nodes": fill_nodes, "policy": policy})
     return out
 
 
