@@ -47,16 +47,20 @@ COUNTERS = os.path.join(ROOT, "profiles", "galilean_droplet_128cube_hbm_counters
 # and writes phi, u*(3), S, M2(6); pressure reads u*(3), P, phi, S and writes
 # P; velocity reads P, u*(3), phi and writes u(3); collide reads phi, u(3),
 # M2(6), h(19) and writes 46 populations.  2-byte storage also reads the
-# previous-step phi in moments and collide (the h codec's reference).  With
-# D3Q19 hydro the populations per node are 38.
+# previous-step phi in moments and collide (the h codec's reference) and the
+# previous-step u in moments (the g codec's reference).  With D3Q19 hydro the
+# populations per node are 38.
 POP_VALUES_3D = 46
 KERNELS = ("moments", "pressure", "velocity", "collide")
 
 
-def kernel_bytes(store_bytes, aux_bytes=4, pops=POP_VALUES_3D):
+def kernel_bytes(store_bytes, aux_bytes=4, pops=POP_VALUES_3D, dim=3):
+    # 2-byte storage: the populations are stored less shifts made of the
+    # previous step's phi (h) and u (g), read back beside them
     ref = aux_bytes if store_bytes == 2 else 0
+    uref = dim * aux_bytes if store_bytes == 2 else 0
     return {
-        "moments": pops * store_bytes + ref + 11 * aux_bytes,
+        "moments": pops * store_bytes + ref + uref + 11 * aux_bytes,
         "pressure": 7 * aux_bytes,
         "velocity": 8 * aux_bytes,
         "collide": 19 * store_bytes + ref + 10 * aux_bytes + pops * store_bytes,
