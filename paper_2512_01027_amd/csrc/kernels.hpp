@@ -6,8 +6,8 @@
 //              phi = sum h, u* = sum g c, P* = rho_ref T sum g (the pressure
 //              the populations carry; the stored rest population lacks the
 //              previous P, which is added back) and M2 = sum g c c.
-//   k_pressure 1-halo LDS tile, FP64 arithmetic: the pressure formula of
-//              Sec. II with K_i of P* and, in the omega term, u* at x - c_i.
+//   k_pressure 1-halo LDS tile: the pressure formula of Sec. II with K_i
+//              of P* and, in the omega term, u* at x - c_i.
 //   k_velocity 1-halo LDS tile: u = sum_i (g_i + K_i) c_i with K_i of the new
 //              pressure, i.e. u = u* - D P / rho.
 //   k_collide  1-halo LDS tile of phi and u: the isotropic central
@@ -326,19 +326,19 @@ __device__ __forceinline__ void aa_store(const Slots<S>& f, uint32_t nb, const N
 // mirror node of a ghost outside a wall (off = t - mirror).  A ghost beyond
 // an open end (wall = 2, high side) takes the nearest node too, marked by
 // kOpenGhost in *crossed instead of counting as a wall crossing.
+// Branch-free, without division: a 1-node halo reaches at most one node past
+// either end, where one +-n wraps exactly.  Cells further out belong only to
+// the halo of nodes outside the grid (a ragged last tile); they are kept
+// inside the grid by the clamp and their values are never used.
 constexpr int kOpenGhost = 256;
 __device__ __forceinline__ int resolve_axis(int t, int n, int wall, int* off, int* crossed)
 {
-    *off = 0;
-    if (t >= 0 && t < n) return t;
-    if (wall) {
-        const int m = t < 0 ? 0 : n - 1;
-        *off = t - m;
-        *crossed += (wall == 2 && t >= n) ? kOpenGhost : 1;
-        return m;
-    }
-    t %= n;
-    return t < 0 ? t + n : t;
+    const bool lo = t < 0, hi = t >= n;
+    const int near = lo ? 0 : (hi ? n - 1 : t);
+    const int wrapped = min(lo ? t + n : (hi ? t - n : t), n - 1);
+    *off = wall ? t - near : 0;
+    *crossed += (wall && (lo || hi)) ? ((wall == 2 && hi) ? kOpenGhost : 1) : 0;
+    return wall ? near : wrapped;
 }
 
 template <int RX, int RY, int RZ>
@@ -383,6 +383,94 @@ struct Halo1 {
         return (uint32_t)m[0] + (uint32_t)cs.sx * ((uint32_t)m[1] + (uint32_t)cs.ny * (uint32_t)m[2]);
     }
 };
+
+// Fills a tile's 1-halo region in LDS from NV arrays (src[j]: node-indexed
+// array of CT).  store(k, cr, off, v) writes cell k from the NV values v of
+// its node, with the crossing flags and wall offsets of Halo1::cell.
+//
+// A tile clear of walls, the open end and the block whose x range lies in the
+// grid takes the row path: each halo row's TX interior cells are read by TX/4
+// lanes with aligned 4-element vector loads (tile origins and row pitches are
+// multiples of 32 nodes), its two end cells by one lane each, in one pass.
+// Only y and z wrap per lane, once per row.
+//
+// Other tiles take the cell path: each thread takes the cells
+// k = threadIdx.x + 256 it, resolves all of them and issues all their loads
+// before the first LDS write, so they are in flight together.  Cells past the
+// region repeat its last cell, and write it too, with the same values as its
+// owner: control flow stays uniform, so no load is sunk into a conditional
+// store.
+template <class HR, int NV, class CT, class StoreF>
+__device__ __forceinline__ void halo_rows(CDesc& cs, const TileCtx& t, void* const* src, StoreF store)
+{
+    using R = typename HR::R;
+    constexpr int TX = HR::RX - 2, ROWS = HR::RY * HR::RZ, LPR = TX / 4;
+    constexpr int NVEC = ROWS * LPR, NEDGE = 2 * ROWS;
+    static_assert(TX % 4 == 0 && NVEC + NEDGE <= 256, "one pass of 256 threads");
+    typedef CT V4 __attribute__((ext_vector_type(4)));
+    const int tid = (int)threadIdx.x;
+    if (tid >= NVEC + NEDGE) return;
+    const bool vec = tid < NVEC;
+    const int r = vec ? tid / LPR : (tid - NVEC) >> 1;
+    const int iy = r % HR::RY, iz = r / HR::RY;
+    int y = t.oy - 1 + iy;
+    y += y < 0 ? cs.ny : (y >= cs.ny ? -cs.ny : 0);
+    y = min(y, cs.ny - 1);
+    int z = t.oz - HR::ZH + iz;
+    z += z < 0 ? cs.nz : (z >= cs.nz ? -cs.nz : 0);
+    z = min(z, cs.nz - 1);
+    const uint32_t row = (uint32_t)cs.sx * ((uint32_t)y + (uint32_t)cs.ny * (uint32_t)z);
+    const int kr = R::idx(0, iy, iz);
+    const int off0[3] = {0, 0, 0};
+    if (vec) {
+        const int q = tid % LPR;
+        const uint32_t m = row + (uint32_t)(t.ox + 4 * q);
+        V4 v[NV];
+#pragma unroll
+        for (int j = 0; j < NV; ++j) v[j] = *(const PULBM_GLB V4*)at_node<CT>(src[j], m);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            CT w[NV];
+#pragma unroll
+            for (int j = 0; j < NV; ++j) w[j] = v[j][e];
+            store(kr + 1 + 4 * q + e, 0, off0, w);
+        }
+    } else {
+        const int side = (tid - NVEC) & 1;
+        int x = side ? t.ox + TX : t.ox - 1;
+        x += x < 0 ? cs.nx : (x >= cs.nx ? -cs.nx : 0);
+        x = min(x, cs.nx - 1);
+        const uint32_t m = row + (uint32_t)x;
+        CT w[NV];
+#pragma unroll
+        for (int j = 0; j < NV; ++j) w[j] = *at_node<CT>(src[j], m);
+        store(kr + (side ? TX + 1 : 0), 0, off0, w);
+    }
+}
+
+template <class HR, bool WALL, int NV, class CT, class StoreF>
+__device__ __forceinline__ void halo_stage(CDesc& cs, const TileCtx& t, void* const* src, StoreF store)
+{
+    if constexpr (!WALL) {
+        if (t.ox + HR::RX - 2 <= cs.nx) {
+            halo_rows<HR, NV, CT>(cs, t, src, store);
+            return;
+        }
+    }
+    constexpr int RN = HR::R::N;
+    constexpr int NIT = (RN + 255) / 256;
+    CT v[NIT][NV];
+    int cr[NIT], off[NIT][3];
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int k = min((int)threadIdx.x + 256 * it, RN - 1);
+        const uint32_t m = HR::template cell<WALL>(cs, t, k, off[it], &cr[it]);
+#pragma unroll
+        for (int j = 0; j < NV; ++j) v[it][j] = *at_node<CT>(src[j], m);
+    }
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) store(min((int)threadIdx.x + 256 * it, RN - 1), cr[it], off[it], v[it]);
+}
 
 // ------------------------------------------------------------ physics
 
@@ -825,8 +913,11 @@ __global__ __launch_bounds__(256) void k_moments(CaseTab cases, const int* hdr, 
 //     + omega rho_ref sum_i w_i c_i . u*(x - c_i), one evaluation of this
 //     equation (which holds P on both sides, through K_i) started from the
 //     pressure the streamed populations carry, P* = rho_ref T sum g: K_i from
-//     P*.  FP64 arithmetic whatever the storage precision; the tile is staged
-//     in LDS in the storage type (exact) and widened at use.
+//     P*.  Arithmetic in the auxiliary type, in difference form: opposite
+//     links enter as P(x - c) - P0 and P(x + c) - P0 and as the difference
+//     u*(x - c) - u*(x + c), each rounded relative to itself, so the sums
+//     carry rounding relative to the gradients, far below the rounding of
+//     the stored P and u*.
 template <int LS, class AT, bool WALL, class R>
 __device__ __forceinline__ void pressure_tile(CDesc& cs, const TileCtx& t, AT* sP, AT* sGD, AT (*sJ)[R::N])
 {
@@ -835,63 +926,75 @@ __device__ __forceinline__ void pressure_tile(CDesc& cs, const TileCtx& t, AT* s
     using G = typename Mo::G;
     using HR = Halo1<Mo, DIMV>;
     const Slots<AT> Js = slots<AT>(cs.J, cs.N);
-    // fixed trip count, fully unrolled: every halo load is issued before the
-    // first LDS write waits on one
-#pragma unroll
-    for (int it = 0; it < (R::N + 255) / 256; ++it) {
-        const int k = threadIdx.x + 256 * it;
-        if (k >= R::N) break;
-        int off[3], cr;
-        const uint32_t m = HR::template cell<WALL>(cs, t, k, off, &cr);
-        sP[k] = *at_node<AT>(cs.Ps, m);
-        // ghost pressure = P(mirror) + rho(x) g.(ghost - mirror): keep g.off;
-        // beyond the open end 2 p_top - P(mirror), p_top half a link out
-        if (WALL) sGD[k] = (AT)(cs.grav[0] * off[0] + cs.grav[1] * off[1] + cs.grav[2] * off[2]);
-        if (WALL && (cr & kOpenGhost)) {
-            sP[k] = (AT)(2.0 * cs.p_top - (double)sP[k]);
-            sGD[k] = 0;
-        }
-#pragma unroll
-        for (int a = 0; a < DIMV; ++a) {
-            AT j = *Js.at(a, m * (uint32_t)sizeof(AT));
-            // u* at a ghost: flow part odd, body-force part even
-            if (WALL && (cr & 1)) j = (AT)(-(double)j + 2.0 * cs.grav[a]);
-            sJ[a][k] = j;
-        }
-    }
-    __syncthreads();
     int lx, ly, lz;
     local_xyz<Mo>(&lx, &ly, &lz);
     const int x = t.ox + lx, y = t.oy + ly, z = t.oz + lz;
-    if (x >= cs.nx || y >= cs.ny || z >= cs.nz) return;
+    const bool live = x < cs.nx && y < cs.ny && z < cs.nz;
     const uint32_t n = (uint32_t)x + (uint32_t)cs.sx * ((uint32_t)y + (uint32_t)cs.ny * (uint32_t)z);
+    // the node's own phi is loaded first, so its latency overlaps the halo's
+    const AT phi = live ? *at_node<AT>(cs.phi[t.step & 1], n) : (AT)0;
+    void* src[1 + DIMV];
+    src[0] = cs.Ps;
+#pragma unroll
+    for (int a = 0; a < DIMV; ++a) src[1 + a] = (void*)Js.at(a, 0);
+    halo_stage<HR, WALL, 1 + DIMV, AT>(
+        cs, t, src,
+        [&](int k, int cr, const int* off, const AT* v) {
+            AT p = v[0], gd = 0;
+            // ghost pressure = P(mirror) + rho(x) g.(ghost - mirror): keep g.off;
+            // beyond the open end 2 p_top - P(mirror), p_top half a link out
+            if (WALL) gd = (AT)(cs.grav[0] * off[0] + cs.grav[1] * off[1] + cs.grav[2] * off[2]);
+            if (WALL && (cr & kOpenGhost)) {
+                p = (AT)(2.0 * cs.p_top - (double)p);
+                gd = 0;
+            }
+            sP[k] = p;
+            if (WALL) sGD[k] = gd;
+#pragma unroll
+            for (int a = 0; a < DIMV; ++a) {
+                AT j = v[1 + a];
+                // u* at a ghost: flow part odd, body-force part even
+                if (WALL && (cr & 1)) j = (AT)(-(double)j + 2.0 * cs.grav[a]);
+                sJ[a][k] = j;
+            }
+        });
+    __syncthreads();
+    if (!live) return;
     if (WALL && in_block(cs, x, y, z)) {
         *at_node<AT>(cs.P[(t.step + 1) & 1], n) = 0;
         return;
     }
-    const double phi = (double)*at_node<AT>(cs.phi[t.step & 1], n);
-    const double ra = cs.rho_a, rw = cs.rho_w;
-    const double pc = phi < 0.0 ? 0.0 : (phi > 1.0 ? 1.0 : phi);
-    const double rho = ra + pc * (rw - ra);
-    const double omega = (rho - ra) / (rw - ra) * (rw / ra - 1.0);
+    // omega = (rho - rho_ref) / rho_ref with omega_max = rho_w / rho_ref, so
+    // (1 + omega) rho_ref / rho = 1 and omega rho_ref = rho - rho_ref
+    const AT drho = clamp01(phi) * (AT)(cs.rho_w - cs.rho_a);
+    const AT rho = (AT)cs.rho_a + drho;
     const int cx = lx + 1, cy = ly + 1, cz = lz + HR::ZH;
-    const double P0 = (double)sP[R::idx(cx, cy, cz)];
-    double sk = 0.0, su = 0.0;
+    const AT P0 = sP[R::idx(cx, cy, cz)];
+    AT sk = 0, du[3] = {0, 0, 0};
 #pragma unroll
-    for (int i = 1; i < G::Q; ++i) {
-        const int k = R::idx(cx - G::c(i, 0), cy - G::c(i, 1), cz - G::c(i, 2));
-        sk += G::w(i) * ((WALL ? (double)sP[k] + rho * (double)sGD[k] : (double)sP[k]) - P0);
-        double cu = 0.0;
+    for (int i = 1; i < G::Q; i += 2) {  // pairs (i, i+1) are opposite
+        const int km = R::idx(cx - G::c(i, 0), cy - G::c(i, 1), cz - G::c(i, 2));
+        const int kp = R::idx(cx + G::c(i, 0), cy + G::c(i, 1), cz + G::c(i, 2));
+        AT dpm = sP[km] - P0, dpp = sP[kp] - P0;
+        if (WALL) {
+            dpm += rho * sGD[km];
+            dpp += rho * sGD[kp];
+        }
+        sk += (AT)G::w(i) * (dpm + dpp);
 #pragma unroll
         for (int a = 0; a < DIMV; ++a) {
-            if (G::c(i, a) == 1) cu += (double)sJ[a][k];
-            if (G::c(i, a) == -1) cu -= (double)sJ[a][k];
+            if (G::c(i, a) == 0) continue;
+            const AT d = (AT)G::w(i) * (sJ[a][km] - sJ[a][kp]);
+            if (G::c(i, a) == 1) du[a] += d;
+            else du[a] -= d;
         }
-        su += G::w(i) * cu;
     }
-    // rho_ref T (1 + omega) K summed = (1 + omega) rho_ref / rho * sum w (dP)
-    const double P = P0 + (1.0 + omega) * ra / rho * sk + omega * ra * su;
-    *at_node<AT>(cs.P[(t.step + 1) & 1], n) = (AT)P;
+    AT su = 0;
+#pragma unroll
+    for (int a = 0; a < DIMV; ++a) su += du[a];
+    // rho_ref T (1 + omega) sum K = (1 + omega) rho_ref / rho * sum w dP = sk
+    const AT P = P0 + (sk + drho * su);
+    *at_node<AT>(cs.P[(t.step + 1) & 1], n) = P;
 }
 
 template <int LS, class AT>
@@ -917,35 +1020,42 @@ __device__ __forceinline__ void velocity_tile(CDesc& cs, const TileCtx& t, CT* s
     using G = typename Mo::G;
     using HR = Halo1<Mo, DIMV>;
     void* Pn = cs.P[(t.step + 1) & 1];
-    // fixed trip count, fully unrolled: every halo load is issued before the
-    // first LDS write waits on one
-#pragma unroll
-    for (int it = 0; it < (R::N + 255) / 256; ++it) {
-        const int k = threadIdx.x + 256 * it;
-        if (k >= R::N) break;
-        int off[3], cr;
-        const uint32_t m = HR::template cell<WALL>(cs, t, k, off, &cr);
-        sP[k] = *at_node<CT>(Pn, m);
-        if (WALL) sGD[k] = (CT)(cs.grav[0] * off[0] + cs.grav[1] * off[1] + cs.grav[2] * off[2]);
-        if (WALL && (cr & kOpenGhost)) {
-            sP[k] = (CT)(2.0 * cs.p_top - (double)sP[k]);
-            sGD[k] = 0;
-        }
-    }
-    __syncthreads();
     int lx, ly, lz;
     local_xyz<Mo>(&lx, &ly, &lz);
     const int x = t.ox + lx, y = t.oy + ly, z = t.oz + lz;
-    if (x >= cs.nx || y >= cs.ny || z >= cs.nz) return;
+    const bool live = x < cs.nx && y < cs.ny && z < cs.nz;
     const uint32_t n = (uint32_t)x + (uint32_t)cs.sx * ((uint32_t)y + (uint32_t)cs.ny * (uint32_t)z);
-    if (WALL && in_block(cs, x, y, z)) {
-        const Slots<CT> Us = slots<CT>(cs.U[t.step & 1], cs.N);
+    const uint32_t na = n * (uint32_t)sizeof(CT);
+    // the node's own operands are loaded first, so their latency overlaps the halo's
+    const Slots<CT> Js = slots<CT>(cs.J, cs.N), Us = slots<CT>(cs.U[t.step & 1], cs.N);
+    CT phi = 0, J[3] = {0, 0, 0};
+    if (live) {
+        phi = *at_node<CT>(cs.phi[t.step & 1], n);
 #pragma unroll
-        for (int a = 0; a < DIMV; ++a) *Us.at(a, n * (uint32_t)sizeof(CT)) = 0;
+        for (int a = 0; a < DIMV; ++a) J[a] = *Js.at(a, na);
+    }
+    void* src[1] = {Pn};
+    halo_stage<HR, WALL, 1, CT>(
+        cs, t, src,
+        [&](int k, int cr, const int* off, const CT* v) {
+            CT p = v[0], gd = 0;
+            if (WALL) gd = (CT)(cs.grav[0] * off[0] + cs.grav[1] * off[1] + cs.grav[2] * off[2]);
+            if (WALL && (cr & kOpenGhost)) {
+                p = (CT)(2.0 * cs.p_top - (double)p);
+                gd = 0;
+            }
+            sP[k] = p;
+            if (WALL) sGD[k] = gd;
+        });
+    __syncthreads();
+    if (!live) return;
+    if (WALL && in_block(cs, x, y, z)) {
+#pragma unroll
+        for (int a = 0; a < DIMV; ++a) *Us.at(a, na) = 0;
         return;
     }
     const CT ra = (CT)cs.rho_a, dr = (CT)(cs.rho_w - cs.rho_a);
-    const CT rho = ra + clamp01(*at_node<CT>(cs.phi[t.step & 1], n)) * dr;
+    const CT rho = ra + clamp01(phi) * dr;
     const CT irho = rcp(rho);
     const int cx = lx + 1, cy = ly + 1, cz = lz + HR::ZH;
     CT gr[3] = {0, 0, 0};
@@ -960,10 +1070,8 @@ __device__ __forceinline__ void velocity_tile(CDesc& cs, const TileCtx& t, CT* s
             if (G::c(i, a) == -1) gr[a] -= d;
         }
     }
-    const Slots<CT> Js = slots<CT>(cs.J, cs.N), Us = slots<CT>(cs.U[t.step & 1], cs.N);
-    const uint32_t na = n * (uint32_t)sizeof(CT);
 #pragma unroll
-    for (int a = 0; a < DIMV; ++a) *Us.at(a, na) = *Js.at(a, na) - gr[a] * (CT)3.0 * irho;
+    for (int a = 0; a < DIMV; ++a) *Us.at(a, na) = J[a] - gr[a] * (CT)3.0 * irho;
 }
 
 template <int LS, class CT>
@@ -1058,23 +1166,18 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
     }
     // halo of phi, rho and u
     const Slots<CT> Us = slots<CT>(cs.U[t.step & 1], cs.N);
-    // fixed trip count, fully unrolled: every halo load is issued before the
-    // first LDS write waits on one
+    void* src[1 + DIMV];
+    src[0] = cs.phi[t.step & 1];
 #pragma unroll
-    for (int it = 0; it < (R::N + 255) / 256; ++it) {
-        const int k = threadIdx.x + 256 * it;
-        if (k >= R::N) break;
-        int off[3], cr;
-        const uint32_t m = HR::template cell<WALL>(cs, t, k, off, &cr);
-        const CT f = *at_node<CT>(cs.phi[t.step & 1], m);
-        sPhi[k] = f;
-        sRho[k] = ph.rho_a + clamp01(f) * ph.drho;
+    for (int a = 0; a < DIMV; ++a) src[1 + a] = (void*)Us.at(a, 0);
+    halo_stage<HR, WALL, 1 + DIMV, CT>(
+        cs, t, src,
+        [&](int k, int cr, const int*, const CT* v) {
+            sPhi[k] = v[0];
+            sRho[k] = ph.rho_a + clamp01(v[0]) * ph.drho;
 #pragma unroll
-        for (int a = 0; a < DIMV; ++a) {
-            const CT ua = *Us.at(a, m * (uint32_t)sizeof(CT));
-            sU[a][k] = (WALL && (cr & 1)) ? -ua : ua;  // no slip on the half-link wall
-        }
-    }
+            for (int a = 0; a < DIMV; ++a) sU[a][k] = (WALL && (cr & 1)) ? -v[1 + a] : v[1 + a];  // no slip
+        });
     if (inside) {
 #pragma unroll
         for (int j = 0; j < H::Q; ++j) sH[j][threadIdx.x] = hraw[j];
