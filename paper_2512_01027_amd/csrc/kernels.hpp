@@ -6,8 +6,8 @@
 //              phi = sum h, u* = sum g c, P* = rho_ref T sum g (the pressure
 //              the populations carry; the stored rest population lacks the
 //              previous P, which is added back) and M2 = sum g c c.
-//   k_pressure 1-halo LDS tile: the pressure formula of Sec. II with K_i
-//              of P* and, in the omega term, u* at x - c_i.
+//   k_pressure 1-halo LDS tile, FP64 sums: the pressure formula of Sec. II
+//              with K_i of P* and, in the omega term, u* at x - c_i.
 //   k_velocity 1-halo LDS tile: u = sum_i (g_i + K_i) c_i with K_i of the new
 //              pressure, i.e. u = u* - D P / rho.
 //   k_collide  1-halo LDS tile of phi and u: the isotropic central
@@ -913,11 +913,10 @@ __global__ __launch_bounds__(256) void k_moments(CaseTab cases, const int* hdr, 
 //     + omega rho_ref sum_i w_i c_i . u*(x - c_i), one evaluation of this
 //     equation (which holds P on both sides, through K_i) started from the
 //     pressure the streamed populations carry, P* = rho_ref T sum g: K_i from
-//     P*.  Arithmetic in the auxiliary type, in difference form: opposite
-//     links enter as P(x - c) - P0 and P(x + c) - P0 and as the difference
-//     u*(x - c) - u*(x + c), each rounded relative to itself, so the sums
-//     carry rounding relative to the gradients, far below the rounding of
-//     the stored P and u*.
+//     P*.  Difference form: opposite links enter as P(x - c) - P0 and
+//     P(x + c) - P0 and as u*(x - c) - u*(x + c), each formed in the
+//     auxiliary type and so rounded relative to itself (exact for P within a
+//     factor 2); sums and the final combination are FP64.
 template <int LS, class AT, bool WALL, class R>
 __device__ __forceinline__ void pressure_tile(CDesc& cs, const TileCtx& t, AT* sP, AT* sGD, AT (*sJ)[R::N])
 {
@@ -965,36 +964,37 @@ __device__ __forceinline__ void pressure_tile(CDesc& cs, const TileCtx& t, AT* s
         return;
     }
     // omega = (rho - rho_ref) / rho_ref with omega_max = rho_w / rho_ref, so
-    // (1 + omega) rho_ref / rho = 1 and omega rho_ref = rho - rho_ref
-    const AT drho = clamp01(phi) * (AT)(cs.rho_w - cs.rho_a);
-    const AT rho = (AT)cs.rho_a + drho;
+    // (1 + omega) rho_ref / rho = 1 and omega rho_ref = rho - rho_ref, which
+    // weights the u* term by up to the density ratio: the sums and this
+    // combination are taken in FP64
+    const double drho = (double)clamp01(phi) * (cs.rho_w - cs.rho_a);
+    const double rho = cs.rho_a + drho;
     const int cx = lx + 1, cy = ly + 1, cz = lz + HR::ZH;
     const AT P0 = sP[R::idx(cx, cy, cz)];
-    AT sk = 0, du[3] = {0, 0, 0};
+    double sk = 0, du[3] = {0, 0, 0};
 #pragma unroll
     for (int i = 1; i < G::Q; i += 2) {  // pairs (i, i+1) are opposite
         const int km = R::idx(cx - G::c(i, 0), cy - G::c(i, 1), cz - G::c(i, 2));
         const int kp = R::idx(cx + G::c(i, 0), cy + G::c(i, 1), cz + G::c(i, 2));
-        AT dpm = sP[km] - P0, dpp = sP[kp] - P0;
+        double dpm = (double)(sP[km] - P0), dpp = (double)(sP[kp] - P0);
         if (WALL) {
-            dpm += rho * sGD[km];
-            dpp += rho * sGD[kp];
+            dpm += rho * (double)sGD[km];
+            dpp += rho * (double)sGD[kp];
         }
-        sk += (AT)G::w(i) * (dpm + dpp);
+        sk += G::w(i) * (dpm + dpp);
 #pragma unroll
         for (int a = 0; a < DIMV; ++a) {
             if (G::c(i, a) == 0) continue;
-            const AT d = (AT)G::w(i) * (sJ[a][km] - sJ[a][kp]);
+            const double d = G::w(i) * (double)(sJ[a][km] - sJ[a][kp]);
             if (G::c(i, a) == 1) du[a] += d;
             else du[a] -= d;
         }
     }
-    AT su = 0;
+    double su = 0;
 #pragma unroll
     for (int a = 0; a < DIMV; ++a) su += du[a];
     // rho_ref T (1 + omega) sum K = (1 + omega) rho_ref / rho * sum w dP = sk
-    const AT P = P0 + (sk + drho * su);
-    *at_node<AT>(cs.P[(t.step + 1) & 1], n) = P;
+    *at_node<AT>(cs.P[(t.step + 1) & 1], n) = (AT)((double)P0 + (sk + drho * su));
 }
 
 template <int LS, class AT>

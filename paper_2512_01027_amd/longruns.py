@@ -144,8 +144,9 @@ def rising_bubble(emit, marks=(1000, 2000, 4000), n=256):
     return ok
 
 
-def dam_break(emit, marks=(5000, 10000, 20000)):
-    cfg, fields, _ = W.config_dam_break_3d(store="fp32")
+def dam_break(emit, marks=(5000, 10000, 20000), nu_light=0.15):
+    cfg, fields, _ = W.config_dam_break_3d(store="fp32", nu_light=nu_light)
+    emit({"run": "dam_break", "nu_water": cfg["nu_heavy"], "nu_air": cfg["nu_light"]})
     ref = _run(cfg, fields, marks, emit, "dam_break", lambda f: (f[0] < 0.5, f[2]))
     got = _run(dict(cfg, store="fp16"), fields, marks, emit, "dam_break", lambda f: f[2])
     for m, (air, u32), u16 in zip(marks, ref, got):
@@ -218,10 +219,13 @@ def main(argv):
     ap.add_argument("--out", default=None)
     ap.add_argument("--store", default="fp16")
     ap.add_argument("--seconds", type=float, default=2.0)
+    ap.add_argument("--nu-light", type=float, default=0.15, help="dam_break: air viscosity")
     args = ap.parse_args(argv)
     emit = _Emit(args.out)
     if args.which == "dam_block":
         ok = dam_block(emit, args.store, args.seconds)
+    elif args.which == "dam_break":
+        ok = dam_break(emit, nu_light=args.nu_light)
     else:
         ok = {"galilean": galilean, "rising_bubble": rising_bubble, "dam_break": dam_break,
               "head_on": head_on}[args.which](emit)

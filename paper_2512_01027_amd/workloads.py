@@ -154,11 +154,11 @@ def config_rising_bubble_3d(n=256, store="fp32", seed=1):
     return cfg, (phi, P, u), 4000
 
 
-def config_dam_break_3d(nx=512, ny=256, nz=256, store="fp16"):
+def config_dam_break_3d(nx=512, ny=256, nz=256, store="fp16", nu_light=0.15):
     """3D nx x ny x nz, walls on all faces, gravity -2e-6 z: water block
-    (nx/4) x ny x (nz/2) in the corner."""
+    (nx/4) x ny x (nz/2) in the corner; nu 0.01 (water) and nu_light (air)."""
     cfg = base_case(3, nx, ny, nz, wall=(1, 1, 1), gravity=(0.0, 0.0, -2e-6), sigma=0.005,
-                    nu_heavy=0.01, nu_light=0.15, W=4.0, store=store)
+                    nu_heavy=0.01, nu_light=nu_light, W=4.0, store=store)
     phi, P, u = dam_block(cfg, nx // 4, nz // 2)
     return cfg, (phi, P, u), 20000
 
