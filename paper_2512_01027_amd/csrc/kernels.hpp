@@ -1164,6 +1164,14 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
             for (int k = 0; k < NM; ++k) m2[k] = *Ms.at(k, na);
         }
     }
+    // 2-byte storage parks h in LDS before the halo loads: the codec's extra
+    // registers leave no room to hold h and every halo value at once
+    if constexpr (sizeof(S) == 2) {
+        if (inside) {
+#pragma unroll
+            for (int j = 0; j < H::Q; ++j) sH[j][threadIdx.x] = hraw[j];
+        }
+    }
     // halo of phi, rho and u
     const Slots<CT> Us = slots<CT>(cs.U[t.step & 1], cs.N);
     void* src[1 + DIMV];
@@ -1178,9 +1186,11 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
 #pragma unroll
             for (int a = 0; a < DIMV; ++a) sU[a][k] = (WALL && (cr & 1)) ? -v[1 + a] : v[1 + a];  // no slip
         });
-    if (inside) {
+    if constexpr (sizeof(S) != 2) {
+        if (inside) {
 #pragma unroll
-        for (int j = 0; j < H::Q; ++j) sH[j][threadIdx.x] = hraw[j];
+            for (int j = 0; j < H::Q; ++j) sH[j][threadIdx.x] = hraw[j];
+        }
     }
     __syncthreads();
     if (!inside) return;
