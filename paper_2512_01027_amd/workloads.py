@@ -163,6 +163,23 @@ def config_dam_break_3d(nx=512, ny=256, nz=256, store="fp16", nu_light=0.15):
     return cfg, (phi, P, u), 20000
 
 
+def config_dam_break_2d(nx=512, ny=256, store="fp32", nu_light=0.05):
+    """The x-z slice of the all-walls dam break as a 2D case (y vertical):
+    walls on all sides, gravity -2e-6 y, water block (nx/4) x (ny/2) in the
+    corner; nu 0.01 (water) and nu_light (air)."""
+    cfg = base_case(2, nx, ny, wall=(1, 1, 0), gravity=(0.0, -2e-6, 0.0), sigma=0.005,
+                    nu_heavy=0.01, nu_light=nu_light, W=4.0, store=store)
+    x, y, _ = _grid(cfg)
+    dx = (nx // 4 - 0.5) - x
+    dy = (ny // 2 - 0.5) - y
+    d = np.minimum(dx, dy)
+    corner = (dx < 0) & (dy < 0)
+    d = np.where(corner, -np.sqrt(dx * dx + dy * dy), d)
+    phi = tanh_profile(d, cfg["W"])
+    P, u = _zero_fields(cfg)
+    return cfg, (phi, P, u)
+
+
 # Dam break against a block (Sec. III): container 3.22 x 1 x 1 m at 5.5 mm
 # per node, water column H = 0.55 m high, block 0.161 x 0.403 x 0.161 m with
 # its near face 0.744 m from the left end, centred across; water 999.10 and
