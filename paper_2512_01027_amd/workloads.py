@@ -71,6 +71,47 @@ def droplet(cfg, R, center=None, u0=None, P0=0.0, heavy_inside=True):
     return phi, P, u
 
 
+def droplet_periodic(cfg, R, center, u0=None):
+    """A heavy droplet of radius R centred anywhere in a periodic box: the
+    distance is taken to the nearest periodic image, so the interface may
+    cross the box's faces.  Built by broadcasting (one full-size temporary at
+    a time), for grids of hundreds of millions of nodes."""
+    nz, ny, nx = cfg["nz"], cfg["ny"], cfg["nx"]
+
+    def axis(n, c):
+        t = np.arange(n, dtype=np.float64) - c
+        return t - n * np.round(t / n)
+
+    dx = axis(nx, center[0])[None, None, :]
+    dy = axis(ny, center[1])[None, :, None]
+    dz = axis(nz, center[2])[:, None, None] if cfg["dim"] == 3 else np.zeros((1, 1, 1))
+    r = dz * dz + (dx * dx + dy * dy)
+    np.sqrt(r, out=r)
+    np.subtract(R, r, out=r)
+    np.multiply(r, 2.0 / cfg["W"], out=r)
+    np.tanh(r, out=r)
+    np.multiply(r, 0.5, out=r)
+    np.add(r, 0.5, out=r)
+    P, u = _zero_fields(cfg)
+    if u0 is not None:
+        for a in range(cfg["dim"]):
+            u[a] += u0[a]
+    return r, P, u
+
+
+def config_droplet_max_grid(store="fp32", shape=(1024, 1024, 511), R=40.0):
+    """The largest 3D grid the library accepts in 4-byte storage:
+    1024 x 1024 x 511 (one field of 4-byte values is just under 2^31 bytes).
+    Periodic; a droplet of radius R whose interface crosses all three pairs
+    of faces (centre 0.6 R short of the high x face, 0.75 R past the low y
+    face and 0.525 R short of the high z face), translated with
+    u = (0.05, 0.02, 0.01); parameters of the 128^3 translated droplet."""
+    nx, ny, nz = shape
+    cfg = base_case(3, nx, ny, nz, sigma=0.005, nu_heavy=0.05, nu_light=0.05, W=4.0, store=store)
+    center = (nx - 0.6 * R, 0.75 * R, nz - 0.525 * R)
+    return cfg, droplet_periodic(cfg, R, center, u0=(0.05, 0.02, 0.01)), center
+
+
 def slab(cfg, lo, hi, axis=0):
     """Heavy layer between two flat interfaces at coordinates lo < hi."""
     x, y, z = _grid(cfg)
