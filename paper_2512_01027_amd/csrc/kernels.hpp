@@ -389,10 +389,9 @@ struct Halo1 {
 // its node, with the crossing flags and wall offsets of Halo1::cell.
 //
 // A tile clear of walls, the open end and the block whose x range lies in the
-// grid takes the row path: each halo row's TX interior cells are read by TX/4
-// lanes with aligned 4-element vector loads (tile origins and row pitches are
-// multiples of 32 nodes), its two end cells by one lane each, in one pass.
-// Only y and z wrap per lane, once per row.
+// grid takes the row path: each halo row's TX interior cells are read as
+// aligned 4-element vectors (tile origins and row pitches are multiples of 32
+// nodes), its two end cells one by one.  Only y and z wrap, once per row.
 //
 // Other tiles take the cell path: each thread takes the cells
 // k = threadIdx.x + 256 it, resolves all of them and issues all their loads
@@ -406,46 +405,63 @@ __device__ __forceinline__ void halo_rows(CDesc& cs, const TileCtx& t, void* con
     using R = typename HR::R;
     constexpr int TX = HR::RX - 2, ROWS = HR::RY * HR::RZ, LPR = TX / 4;
     constexpr int NVEC = ROWS * LPR, NEDGE = 2 * ROWS;
-    static_assert(TX % 4 == 0 && NVEC + NEDGE <= 256, "one pass of 256 threads");
+    constexpr int PV = (NVEC + 255) / 256, PE = (NEDGE + 255) / 256;
+    static_assert(TX % 4 == 0, "rows of 4-element vectors");
     typedef CT V4 __attribute__((ext_vector_type(4)));
     const int tid = (int)threadIdx.x;
-    if (tid >= NVEC + NEDGE) return;
-    const bool vec = tid < NVEC;
-    const int r = vec ? tid / LPR : (tid - NVEC) >> 1;
-    const int iy = r % HR::RY, iz = r / HR::RY;
-    int y = t.oy - 1 + iy;
-    y += y < 0 ? cs.ny : (y >= cs.ny ? -cs.ny : 0);
-    y = min(y, cs.ny - 1);
-    int z = t.oz - HR::ZH + iz;
-    z += z < 0 ? cs.nz : (z >= cs.nz ? -cs.nz : 0);
-    z = min(z, cs.nz - 1);
-    const uint32_t row = (uint32_t)cs.sx * ((uint32_t)y + (uint32_t)cs.ny * (uint32_t)z);
-    const int kr = R::idx(0, iy, iz);
     const int off0[3] = {0, 0, 0};
-    if (vec) {
-        const int q = tid % LPR;
-        const uint32_t m = row + (uint32_t)(t.ox + 4 * q);
-        V4 v[NV];
+    // node index of the start of halo row r, and its first LDS cell
+    auto row_of = [&](int r, int* kr) {
+        const int iy = r % HR::RY, iz = r / HR::RY;
+        int y = t.oy - 1 + iy;
+        y += y < 0 ? cs.ny : (y >= cs.ny ? -cs.ny : 0);
+        y = min(y, cs.ny - 1);
+        int z = t.oz - HR::ZH + iz;
+        z += z < 0 ? cs.nz : (z >= cs.nz ? -cs.nz : 0);
+        z = min(z, cs.nz - 1);
+        *kr = R::idx(0, iy, iz);
+        return (uint32_t)cs.sx * ((uint32_t)y + (uint32_t)cs.ny * (uint32_t)z);
+    };
+    // items past the last one repeat it (same loads, same LDS cells, same
+    // values), so every load is unconditional and issued before any store
+    V4 v[PV][NV];
+    int kv[PV];
 #pragma unroll
-        for (int j = 0; j < NV; ++j) v[j] = *(const PULBM_GLB V4*)at_node<CT>(src[j], m);
+    for (int p = 0; p < PV; ++p) {
+        const int it = min(tid + 256 * p, NVEC - 1);
+        const int q = it % LPR;
+        int kr;
+        const uint32_t m = row_of(it / LPR, &kr) + (uint32_t)(t.ox + 4 * q);
+        kv[p] = kr + 1 + 4 * q;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            CT w[NV];
+        for (int j = 0; j < NV; ++j) v[p][j] = *(const PULBM_GLB V4*)at_node<CT>(src[j], m);
+    }
+    CT e[PE][NV];
+    int ke[PE];
 #pragma unroll
-            for (int j = 0; j < NV; ++j) w[j] = v[j][e];
-            store(kr + 1 + 4 * q + e, 0, off0, w);
-        }
-    } else {
-        const int side = (tid - NVEC) & 1;
+    for (int p = 0; p < PE; ++p) {
+        const int it = min(tid + 256 * p, NEDGE - 1);
+        const int side = it & 1;
+        int kr;
+        const uint32_t row = row_of(it >> 1, &kr);
         int x = side ? t.ox + TX : t.ox - 1;
         x += x < 0 ? cs.nx : (x >= cs.nx ? -cs.nx : 0);
         x = min(x, cs.nx - 1);
-        const uint32_t m = row + (uint32_t)x;
-        CT w[NV];
+        ke[p] = kr + (side ? TX + 1 : 0);
 #pragma unroll
-        for (int j = 0; j < NV; ++j) w[j] = *at_node<CT>(src[j], m);
-        store(kr + (side ? TX + 1 : 0), 0, off0, w);
+        for (int j = 0; j < NV; ++j) e[p][j] = *at_node<CT>(src[j], row + (uint32_t)x);
     }
+#pragma unroll
+    for (int p = 0; p < PV; ++p)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            CT w[NV];
+#pragma unroll
+            for (int j = 0; j < NV; ++j) w[j] = v[p][j][c];
+            store(kv[p] + c, 0, off0, w);
+        }
+#pragma unroll
+    for (int p = 0; p < PE; ++p) store(ke[p], 0, off0, e[p]);
 }
 
 template <class HR, bool WALL, int NV, class CT, class StoreF>

@@ -60,7 +60,8 @@ struct Layout {
 };
 
 // Row pitch of every field: nx rounded up to 32 nodes, so that a tile row
-// (32 nodes in 3D, 64 in 2D) starts on a 128-byte line whatever nx is.
+// (64 nodes, at an x origin that is a multiple of 64) starts on a 128-byte
+// line whatever nx is.
 int row_pitch(int nx) { return (nx + 31) & ~31; }
 
 Layout make_layout(const pulbm_params& p)

@@ -54,6 +54,10 @@ CASES = {
     "3d_periodic_ragged": dict(dim=3, nx=37, ny=10, nz=7),
     "3d_walls_z_gravity": dict(dim=3, nx=33, ny=9, nz=8, wall=(0, 0, 1), gravity=(0.0, 0.0, -1e-5)),
     "3d_all_walls": dict(dim=3, nx=20, ny=7, nz=9, wall=(1, 1, 1), gravity=(1e-6, 2e-6, -1e-5)),
+    # wider than a tile in x: full tiles read their halo rows as vectors,
+    # the ragged last one cell by cell
+    "3d_periodic_wide": dict(dim=3, nx=70, ny=9, nz=7),
+    "3d_walls_y_wide": dict(dim=3, nx=130, ny=8, nz=6, wall=(0, 1, 0), gravity=(0.0, -1e-5, 0.0)),
 }
 
 
@@ -149,7 +153,7 @@ def test_static_droplet_2d_config_full_run():
 
 
 @pytest.mark.parametrize("store,tol", [("fp32", 2e-5)])
-@pytest.mark.parametrize("case", ["3d_walls_z_gravity", "2d_walls_gravity"])
+@pytest.mark.parametrize("case", ["3d_walls_z_gravity", "2d_walls_gravity", "3d_walls_y_wide"])
 def test_fp32_matches_oracle(store, tol, case):
     kw = dict(CASES[case])
     dim, nx, ny = kw.pop("dim"), kw.pop("nx"), kw.pop("ny")
@@ -224,13 +228,21 @@ def test_graph_replay_equals_direct_launches(store):
 
 
 @pytest.mark.parametrize("store,tol", [("fp64", TOL64), ("fp32", 2e-5)])
-@pytest.mark.parametrize("case", ["2d_walls_gravity", "3d_periodic_ragged", "3d_all_walls"])
+@pytest.mark.parametrize("case", ["2d_walls_gravity", "3d_periodic_ragged", "3d_all_walls", "3d_periodic_wide"])
 def test_bgk_collision_matches_oracle(case, store, tol):
     """The BGK hydrodynamic collision (Eq. BGK_LBeq_hydroeq, collision = 1)
-    at nu = 0.1, where it is stable at density ratio 1000."""
+    at nu = 0.1, where it is stable at density ratio 1000.
+
+    FP32 runs without delta theta: its sign switch s = L phi / (|L phi| + eps)
+    makes the map discontinuous where L phi is at FP32 rounding level, which
+    on 3d_periodic_wide (phi between 1e-4 and 0.2, where the switch acts,
+    over most of the box) moves the FP32 result by 7e-3 under a 1e-7
+    perturbation of phi0.  FP64 keeps it."""
     kw = dict(CASES[case])
     dim, nx, ny = kw.pop("dim"), kw.pop("nx"), kw.pop("ny")
     nz = kw.pop("nz", 1)
+    if store != "fp64":
+        kw["delta_theta"] = 0
     cfg = W.base_case(dim, nx, ny, nz, nu_heavy=0.1, nu_light=0.1, store=store, collision="bgk", **kw)
     f = _fields(cfg)
     g = B.Case(cfg)
@@ -245,7 +257,7 @@ def test_bgk_collision_matches_oracle(case, store, tol):
 
 @pytest.mark.parametrize("store,tol", [("fp64", TOL64), ("fp32", 2e-5)])
 @pytest.mark.parametrize("collision", ["filter", "bgk"])
-@pytest.mark.parametrize("case", ["3d_periodic_ragged", "3d_walls_z_gravity", "3d_all_walls"])
+@pytest.mark.parametrize("case", ["3d_periodic_ragged", "3d_walls_z_gravity", "3d_all_walls", "3d_periodic_wide"])
 def test_d3q19_hydro_matches_oracle(case, collision, store, tol):
     """D3Q19 for the hydrodynamic populations as well as the phase field
     (the lattice of the paper's 3D runs, Sec. II)."""
