@@ -70,7 +70,7 @@ struct CaseDev {
     double p_top;           // pressure of an open high end (wall = 2 on the last axis)
     int32_t blk_lo[3], blk_hi[3];  // solid block, nodes lo <= x < hi (has_block)
     int32_t has_block;
-    int32_t pad1;
+    int32_t tband;  // tile rows per y band of the tile order (>= 1)
 };
 
 using CDesc = const PULBM_CST CaseDev;
@@ -141,11 +141,18 @@ __device__ __forceinline__ TileCtx tile_ctx(CaseTab cases, const int* hdr_, int 
     // whatever the case's step limit)
     t.step = cs.step + (step_off > 0 ? step_off : 0);
     t.active = step_off < 0 || t.step < cs.step_end;
+    // tile order: x fastest, then z within a band of tband tile rows, then
+    // the bands along y.  Tiles that share z-halo rows then run close together
+    // (a band's width of tiles apart), while each plane is still read in runs
+    // of whole rows.
     int lt = tile - tstart[ci];
     const int tx = lt % cs.ntx;
     lt /= cs.ntx;
-    const int ty = lt % cs.nty;
-    const int tz = lt / cs.nty;
+    const int yb = lt / (cs.tband * cs.ntz);
+    const int rem = lt - yb * cs.tband * cs.ntz;
+    const int by = min(cs.tband, cs.nty - yb * cs.tband);
+    const int tz = rem / by;
+    const int ty = yb * cs.tband + rem % by;
     t.ox = tx * Mo::TX;
     t.oy = ty * Mo::TY;
     t.oz = tz * Mo::TZ;

@@ -353,6 +353,9 @@ extern "C" int pulbm_create(const pulbm_params* p, void* dev_arena, size_t arena
     if (p->dim == 2) tiles_of<2>(*p, &h.ntx, &h.nty, &h.ntz);
     else tiles_of<3>(*p, &h.ntx, &h.nty, &h.ntz);
     c->ntiles = h.ntx * h.nty * h.ntz;
+    // y bands of about 64 tiles per z layer: z neighbours then run within
+    // what one XCD holds at once (measured: 128^3 +1%, 256^3 +6%)
+    h.tband = std::max(4, std::min(32, 64 / h.ntx));
     h.delta_theta = p->delta_theta;
     h.sx = row_pitch(p->nx);
     h.N = (int64_t)h.sx * p->ny * p->nz;
