@@ -936,10 +936,11 @@ __global__ __launch_bounds__(256) void k_moments(CaseTab cases, const int* hdr, 
 //     + omega rho_ref sum_i w_i c_i . u*(x - c_i), one evaluation of this
 //     equation (which holds P on both sides, through K_i) started from the
 //     pressure the streamed populations carry, P* = rho_ref T sum g: K_i from
-//     P*.  Difference form: opposite links enter as P(x - c) - P0 and
-//     P(x + c) - P0 and as u*(x - c) - u*(x + c), each formed in the
-//     auxiliary type and so rounded relative to itself (exact for P within a
-//     factor 2); sums and the final combination are FP64.
+//     P*.  Difference form: opposite links enter as
+//     (P(x - c) - P0) + (P(x + c) - P0) and as u*(x - c) - u*(x + c), each
+//     formed in the auxiliary type and so rounded relative to itself (the
+//     single differences exact for P within a factor 2); the sums over the
+//     links and the final combination are FP64.
 template <int LS, class AT, bool WALL, class R>
 __device__ __forceinline__ void pressure_tile(CDesc& cs, const TileCtx& t, AT* sP, AT* sGD, AT (*sJ)[R::N])
 {
@@ -999,12 +1000,11 @@ __device__ __forceinline__ void pressure_tile(CDesc& cs, const TileCtx& t, AT* s
     for (int i = 1; i < G::Q; i += 2) {  // pairs (i, i+1) are opposite
         const int km = R::idx(cx - G::c(i, 0), cy - G::c(i, 1), cz - G::c(i, 2));
         const int kp = R::idx(cx + G::c(i, 0), cy + G::c(i, 1), cz + G::c(i, 2));
-        double dpm = (double)(sP[km] - P0), dpp = (double)(sP[kp] - P0);
-        if (WALL) {
-            dpm += rho * (double)sGD[km];
-            dpp += rho * (double)sGD[kp];
-        }
-        sk += G::w(i) * (dpm + dpp);
+        // the pair's two differences are added before widening (a second
+        // difference, rounded relative to itself); the sum over pairs is FP64
+        double dp = (double)((sP[km] - P0) + (sP[kp] - P0));
+        if (WALL) dp += rho * ((double)sGD[km] + (double)sGD[kp]);
+        sk += G::w(i) * dp;
 #pragma unroll
         for (int a = 0; a < DIMV; ++a) {
             if (G::c(i, a) == 0) continue;
