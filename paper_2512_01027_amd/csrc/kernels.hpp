@@ -35,6 +35,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "codec.hpp"
 #include "lattice.hpp"
@@ -770,13 +771,6 @@ __device__ __forceinline__ void stencil(F q, int cx, int cy, int cz, CT grad[3],
     if (lap) *lap = l * (CT)6.0;                             // 2/T
 }
 
-// Keeps the scheduler from hoisting the loads of a later phase into an
-// earlier one (which would hold their registers across both).
-#ifndef PULBM_NO_PHASE_FENCE
-#define PULBM_PHASE_FENCE() __builtin_amdgcn_sched_barrier(0)
-#else
-#define PULBM_PHASE_FENCE() ((void)0)
-#endif
 
 template <class Mo>
 __device__ __forceinline__ void local_xyz(int* lx, int* ly, int* lz)
@@ -1123,7 +1117,6 @@ __device__ __forceinline__ void tile_gradients(const CT* sPhi, const CT* sRho, c
 #pragma unroll
     for (int a = 0; a < 3; ++a) v.u[a] = a < DIMV ? sU[a][c0] : (CT)0;
     stencil<G, R, CT>([&](int k) { return sPhi[k]; }, cx, cy, cz, v.gphi, &v.lphi);
-    PULBM_PHASE_FENCE();
     stencil<G, R, CT>([&](int k) { return sRho[k]; }, cx, cy, cz, v.grho, (CT*)nullptr);
 #pragma unroll
     for (int a = 0; a < 3; ++a)
@@ -1131,13 +1124,11 @@ __device__ __forceinline__ void tile_gradients(const CT* sPhi, const CT* sRho, c
         for (int b = 0; b < 3; ++b) v.G[a][b] = 0;
 #pragma unroll
     for (int a = 0; a < DIMV; ++a) {
-        PULBM_PHASE_FENCE();
         CT gr[3];
         stencil<G, R, CT>([&](int k) { return sU[a][k]; }, cx, cy, cz, gr, (CT*)nullptr);
 #pragma unroll
         for (int b = 0; b < DIMV; ++b) v.G[a][b] = gr[b];
     }
-    PULBM_PHASE_FENCE();
 }
 
 // --- collide + stream.  A tile first issues the loads of its own nodes'
@@ -1272,10 +1263,11 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
     CT hmoved = 0;
 #pragma unroll
     for (int i = 1; i < G::Q; i += 2) {
-        // 2-byte storage: keep the scheduler from interleaving pairs (the
-        // codec shifts' LDS reads, hoisted across pairs, push the D3Q27
-        // kernel past its register budget into scratch spills)
-        if constexpr (sizeof(S) == 2) PULBM_PHASE_FENCE();
+        // BF16 storage: keep the scheduler from interleaving pairs (its
+        // codec's integer rounding, hoisted across pairs, pushes the D3Q27
+        // kernel past its register budget into scratch spills; FP16 storage
+        // runs faster without the barrier)
+        if constexpr (std::is_same_v<S, uint16_t>) __builtin_amdgcn_sched_barrier(0);
         const bool bi = WALL && nav_solid<G>(nv, i, +1);
         const bool bk = WALL && nav_solid<G>(nv, i + 1, +1);
         CT gi, gk;
