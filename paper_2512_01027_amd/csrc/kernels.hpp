@@ -72,6 +72,10 @@ struct CaseDev {
     int32_t blk_lo[3], blk_hi[3];  // solid block, nodes lo <= x < hi (has_block)
     int32_t has_block;
     int32_t tband;  // tile rows per y band of the tile order (>= 1)
+    int32_t fuse_u; // 1: the collide kernel rebuilds u itself and a step skips k_velocity
+                    // (no wall, open end or block, 4- or 8-byte storage, every axis >= 3,
+                    // D2Q9 or D3Q19 hydro)
+    int32_t pad1;
 };
 
 using CDesc = const PULBM_CST CaseDev;
@@ -358,6 +362,7 @@ struct Region {
 // 1-halo region of a tile: cell k -> mirror node index, wall offsets, crossings.
 template <class Mo, int DIMV>
 struct Halo1 {
+    static constexpr int D = 1;  // halo depth
     static constexpr int ZH = DIMV == 3 ? 1 : 0;
     static constexpr int RX = Mo::TX + 2, RY = Mo::TY + 2, RZ = Mo::TZ + 2 * ZH;
     using R = Region<RX, RY, RZ>;
@@ -392,6 +397,28 @@ struct Halo1 {
     }
 };
 
+// 2-halo region of a tile on a grid without walls, open end or block and
+// with every axis of at least 3 nodes, so that one +-n wraps a coordinate
+// two nodes past either end.
+template <class Mo, int DIMV>
+struct Halo2 {
+    static constexpr int D = 2;
+    static constexpr int ZH = DIMV == 3 ? 2 : 0;
+    static constexpr int RX = Mo::TX + 4, RY = Mo::TY + 4, RZ = Mo::TZ + 2 * ZH;
+    using R = Region<RX, RY, RZ>;
+    template <bool BND = false>
+    __device__ static __forceinline__ uint32_t cell(CDesc& cs, const TileCtx& t, int k, int off[3], int* cr)
+    {
+        static_assert(!BND, "periodic grids only");
+        const int ix = k % RX, iy = (k / RX) % RY, iz = k / (RX * RY);
+        *cr = 0;
+        const int x = resolve_axis(t.ox - 2 + ix, cs.nx, 0, &off[0], cr);
+        const int y = resolve_axis(t.oy - 2 + iy, cs.ny, 0, &off[1], cr);
+        const int z = resolve_axis(t.oz - ZH + iz, cs.nz, 0, &off[2], cr);
+        return (uint32_t)x + (uint32_t)cs.sx * ((uint32_t)y + (uint32_t)cs.ny * (uint32_t)z);
+    }
+};
+
 // Fills a tile's 1-halo region in LDS from NV arrays (src[j]: node-indexed
 // array of CT).  store(k, cr, off, v) writes cell k from the NV values v of
 // its node, with the crossing flags and wall offsets of Halo1::cell.
@@ -411,8 +438,8 @@ template <class HR, int NV, class CT, class StoreF>
 __device__ __forceinline__ void halo_rows(CDesc& cs, const TileCtx& t, void* const* src, StoreF store)
 {
     using R = typename HR::R;
-    constexpr int TX = HR::RX - 2, ROWS = HR::RY * HR::RZ, LPR = TX / 4;
-    constexpr int NVEC = ROWS * LPR, NEDGE = 2 * ROWS;
+    constexpr int DH = HR::D, TX = HR::RX - 2 * DH, ROWS = HR::RY * HR::RZ, LPR = TX / 4;
+    constexpr int NVEC = ROWS * LPR, NEDGE = 2 * DH * ROWS;
     constexpr int PV = (NVEC + 255) / 256, PE = (NEDGE + 255) / 256;
     static_assert(TX % 4 == 0, "rows of 4-element vectors");
     typedef CT V4 __attribute__((ext_vector_type(4)));
@@ -421,7 +448,7 @@ __device__ __forceinline__ void halo_rows(CDesc& cs, const TileCtx& t, void* con
     // node index of the start of halo row r, and its first LDS cell
     auto row_of = [&](int r, int* kr) {
         const int iy = r % HR::RY, iz = r / HR::RY;
-        int y = t.oy - 1 + iy;
+        int y = t.oy - DH + iy;
         y += y < 0 ? cs.ny : (y >= cs.ny ? -cs.ny : 0);
         y = min(y, cs.ny - 1);
         int z = t.oz - HR::ZH + iz;
@@ -440,7 +467,7 @@ __device__ __forceinline__ void halo_rows(CDesc& cs, const TileCtx& t, void* con
         const int q = it % LPR;
         int kr;
         const uint32_t m = row_of(it / LPR, &kr) + (uint32_t)(t.ox + 4 * q);
-        kv[p] = kr + 1 + 4 * q;
+        kv[p] = kr + DH + 4 * q;
 #pragma unroll
         for (int j = 0; j < NV; ++j) v[p][j] = *(const PULBM_GLB V4*)at_node<CT>(src[j], m);
     }
@@ -449,13 +476,13 @@ __device__ __forceinline__ void halo_rows(CDesc& cs, const TileCtx& t, void* con
 #pragma unroll
     for (int p = 0; p < PE; ++p) {
         const int it = min(tid + 256 * p, NEDGE - 1);
-        const int side = it & 1;
+        const int side = it % (2 * DH);  // 0 .. DH-1 before the row, DH .. 2DH-1 after it
         int kr;
-        const uint32_t row = row_of(it >> 1, &kr);
-        int x = side ? t.ox + TX : t.ox - 1;
+        const uint32_t row = row_of(it / (2 * DH), &kr);
+        int x = side < DH ? t.ox - DH + side : t.ox + TX + side - DH;
         x += x < 0 ? cs.nx : (x >= cs.nx ? -cs.nx : 0);
         x = min(x, cs.nx - 1);
-        ke[p] = kr + (side ? TX + 1 : 0);
+        ke[p] = kr + (side < DH ? side : TX + side);
 #pragma unroll
         for (int j = 0; j < NV; ++j) e[p][j] = *at_node<CT>(src[j], row + (uint32_t)x);
     }
@@ -476,7 +503,7 @@ template <class HR, bool WALL, int NV, class CT, class StoreF>
 __device__ __forceinline__ void halo_stage(CDesc& cs, const TileCtx& t, void* const* src, StoreF store)
 {
     if constexpr (!WALL) {
-        if (t.ox + HR::RX - 2 <= cs.nx) {
+        if (t.ox + HR::RX - 2 * HR::D <= cs.nx) {
             halo_rows<HR, NV, CT>(cs, t, src, store);
             return;
         }
@@ -1101,6 +1128,8 @@ __global__ __launch_bounds__(256) void k_velocity(CaseTab cases, const int* hdr,
     const TileCtx t = tile_ctx<Mo>(cases, hdr, step_off);
     if (!t.active) return;
     CDesc& cs = *t.cs;
+    // a fused case's collide rebuilds u itself; the read pass (step_off < 0) still needs it here
+    if (cs.fuse_u && step_off >= 0) return;
     if (tile_at_wall<Mo>(cs, t.ox, t.oy, t.oz)) velocity_tile<LS, CT, true, R>(cs, t, sP, sGD);
     else velocity_tile<LS, CT, false, R>(cs, t, sP, sGD);
 }
@@ -1138,7 +1167,8 @@ __device__ __forceinline__ void tile_gradients(const CT* sPhi, const CT* sRho, c
 template <int LS, class S, bool WALL, bool BGK, class R>
 __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typename Codec<S>::CT* sPhi,
                                              typename Codec<S>::CT* sRho,
-                                             typename Codec<S>::CT (*sU)[R::N], S (*sH)[256])
+                                             typename Codec<S>::CT (*sU)[R::N], S (*sH)[256],
+                                             typename Codec<S>::CT* sP2)
 {
     constexpr int DIMV = Model<LS>::DIM;
     using Mo = Model<LS>;
@@ -1186,8 +1216,12 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
             for (int j = 0; j < H::Q; ++j) sH[j][threadIdx.x] = hraw[j];
         }
     }
-    // halo of phi, rho and u
-    const Slots<CT> Us = slots<CT>(cs.U[t.step & 1], cs.N);
+    // halo of phi, rho and u; a fused case (no wall, open end or block)
+    // loads u* instead of u and the new P two nodes deep, and rebuilds u
+    // itself below
+    bool fused = false;
+    if constexpr (!WALL && sizeof(S) >= 4) fused = cs.fuse_u;
+    const Slots<CT> Us = slots<CT>(fused ? cs.J : cs.U[t.step & 1], cs.N);
     void* src[1 + DIMV];
     src[0] = cs.phi[t.step & 1];
 #pragma unroll
@@ -1200,6 +1234,13 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
 #pragma unroll
             for (int a = 0; a < DIMV; ++a) sU[a][k] = (WALL && (cr & 1)) ? -v[1 + a] : v[1 + a];  // no slip
         });
+    if constexpr (!WALL && sizeof(S) >= 4) {
+        if (fused) {
+            void* psrc[1] = {cs.P[(t.step + 1) & 1]};
+            halo_stage<Halo2<Mo, DIMV>, false, 1, CT>(cs, t, psrc,
+                                                      [&](int k, int, const int*, const CT* v) { sP2[k] = v[0]; });
+        }
+    }
     if constexpr (sizeof(S) != 2) {
         if (inside) {
 #pragma unroll
@@ -1207,6 +1248,38 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
         }
     }
     __syncthreads();
+    if constexpr (!WALL && sizeof(S) >= 4) {
+        if (fused) {
+            // u = u* - D P / rho at every cell of the 1-halo region, the
+            // expression of k_velocity term by term
+            using R2 = typename Halo2<Mo, DIMV>::R;
+            constexpr int DZ = Halo2<Mo, DIMV>::ZH - HR::ZH;
+#pragma unroll
+            for (int it = 0; it < (R::N + 255) / 256; ++it) {
+                const int k = (int)threadIdx.x + 256 * it;
+                if (k < R::N) {
+                    const int ix = k % HR::RX, iy = (k / HR::RX) % HR::RY, iz = k / (HR::RX * HR::RY);
+                    const int cx2 = ix + 1, cy2 = iy + 1, cz2 = iz + DZ;
+                    CT gr[3] = {0, 0, 0};
+#pragma unroll
+                    for (int i = 1; i < G::Q; i += 2) {
+                        const int kp = R2::idx(cx2 + G::c(i, 0), cy2 + G::c(i, 1), cz2 + G::c(i, 2));
+                        const int km = R2::idx(cx2 - G::c(i, 0), cy2 - G::c(i, 1), cz2 - G::c(i, 2));
+                        const CT d = (sP2[kp] - sP2[km]) * (CT)G::w(i);
+#pragma unroll
+                        for (int a = 0; a < DIMV; ++a) {
+                            if (G::c(i, a) == 1) gr[a] += d;
+                            if (G::c(i, a) == -1) gr[a] -= d;
+                        }
+                    }
+                    const CT irho = rcp(sRho[k]);
+#pragma unroll
+                    for (int a = 0; a < DIMV; ++a) sU[a][k] = sU[a][k] - gr[a] * (CT)3.0 * irho;
+                }
+            }
+            __syncthreads();
+        }
+    }
     if (!inside) return;
 
     NodeVals<CT> v;
@@ -1354,11 +1427,13 @@ __global__ __launch_bounds__(256) PULBM_COLLIDE_ATTR void k_collide(CaseTab case
     using R = typename Halo1<Mo, DIMV>::R;
     __shared__ CT sPhi[R::N], sRho[R::N], sU[DIMV][R::N];
     __shared__ S sH[H::Q][256];
+    // the new P two nodes deep, for cases whose collide rebuilds u (4- and 8-byte storage)
+    __shared__ CT sP2[sizeof(S) >= 4 ? Halo2<Mo, DIMV>::R::N : 1];
     const TileCtx t = tile_ctx<Mo>(cases, hdr, step_off);
     if (!t.active) return;
     CDesc& cs = *t.cs;
-    if (tile_at_wall<Mo>(cs, t.ox, t.oy, t.oz)) collide_tile<LS, S, true, BGK, R>(cs, t, sPhi, sRho, sU, sH);
-    else collide_tile<LS, S, false, BGK, R>(cs, t, sPhi, sRho, sU, sH);
+    if (tile_at_wall<Mo>(cs, t.ox, t.oy, t.oz)) collide_tile<LS, S, true, BGK, R>(cs, t, sPhi, sRho, sU, sH, sP2);
+    else collide_tile<LS, S, false, BGK, R>(cs, t, sPhi, sRho, sU, sH, sP2);
 }
 
 // --- initial state: equilibria of (phi0, P0, u0) in the even AA layout,

@@ -162,6 +162,7 @@ template <int LS> void tiles_of(const pulbm_params& p, int* ntx, int* nty, int* 
 int grid_of(int tiles) { return ((tiles + 7) / 8) * 8; }
 
 constexpr int kStepKernels = 4;  // moments, pressure, velocity, collide + stream
+constexpr int kVelocityKernel = 2;
 constexpr int kReadKernels = 3;  // the moment stage only
 
 }  // namespace
@@ -377,6 +378,14 @@ extern "C" int pulbm_create(const pulbm_params* p, void* dev_arena, size_t arena
         h.blk_lo[a] = h.has_block ? p->block_lo[a] : 0;
         h.blk_hi[a] = h.has_block ? p->block_hi[a] : 0;
     }
+    // the collide kernel rebuilds u from a 2-node halo of the new P where
+    // every tile is clear of walls, the open end and the block, and one
+    // +-n wraps two nodes past either end of every axis.  Measured at 128^3:
+    // with D3Q19 and D2Q9 hydro (9 and 4 direction pairs) this saves more
+    // than it adds to the collide kernel; with D3Q27 (13 pairs) the two
+    // cancel, and the separate velocity kernel is kept.
+    h.fuse_u = !h.has_block && !p->wall[0] && !p->wall[1] && !p->wall[2] && store_bytes(p->store) >= 4 &&
+               p->nx >= 3 && p->ny >= 3 && (p->dim == 2 || (p->nz >= 3 && p->q_hydro == 19));
     codec_constants(*p, h);
     c->d = (CaseDev*)(c->base + L.desc);
     c->tab = (CaseDev**)(c->base + L.tab);
@@ -457,7 +466,8 @@ static void queue_direct(pulbm_case* c, int count)
 {
     for (int k = 0; k < count; ++k)
         for (int w = 0; w < kStepKernels; ++w)
-            launch(lattice_set(c->p.dim, c->p.q_hydro), c->p.store, c->p.collision == 1, c->stream, c->tab, c->hdr, grid_of(c->ntiles), k, w);
+            if (w != kVelocityKernel || !c->h.fuse_u)
+                launch(lattice_set(c->p.dim, c->p.q_hydro), c->p.store, c->p.collision == 1, c->stream, c->tab, c->hdr, grid_of(c->ntiles), k, w);
     hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, c->stream, c->tab, c->hdr, count);
 }
 
@@ -493,7 +503,8 @@ extern "C" int pulbm_step_timed(pulbm_case* c, int64_t nsteps, double* ms)
     for (int64_t s = 0; s < nsteps && rc == PULBM_OK; ++s) {
         (void)hipEventRecord(ev[0], c->stream);
         for (int w = 0; w < kStepKernels; ++w) {
-            launch(lattice_set(c->p.dim, c->p.q_hydro), c->p.store, c->p.collision == 1, c->stream, c->tab, c->hdr, grid_of(c->ntiles), 0, w);
+            if (w != kVelocityKernel || !c->h.fuse_u)
+                launch(lattice_set(c->p.dim, c->p.q_hydro), c->p.store, c->p.collision == 1, c->stream, c->tab, c->hdr, grid_of(c->ntiles), 0, w);
             (void)hipEventRecord(ev[w + 1], c->stream);
         }
         hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, c->stream, c->tab, c->hdr, 1);
