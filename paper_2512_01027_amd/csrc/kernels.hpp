@@ -13,7 +13,10 @@
 //   k_collide  1-halo LDS tile of phi and u: the isotropic central
 //              differences of phi, rho and u, the BGK phase-field collision
 //              and the filter collision of the hydrodynamic LBE, written back
-//              in place (AA pattern).
+//              in place (AA pattern).  Cases without walls, open end or block
+//              on D3Q19 or D2Q9 hydro (with 4- or 8-byte storage) rebuild u
+//              here from u* and a 2-node halo of the new P, and a step skips
+//              k_velocity.
 //
 // Memory layout (per case): structure of arrays, x fastest; population i of
 // node n at f[i*N + n].  AA pattern: on even steps node x reads slot i of x
