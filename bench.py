@@ -205,10 +205,10 @@ def table1_leg(t_end=1.0, samples=4):
     return out
 
 
-def workloads_leg(steps=100, warmup=10):
+def workloads_leg(steps=100, warmup=10, only=None, only_store=None):
     """MLUPS, effective HBM GB/s (state bytes per node update x MLUPS) and the
     collide kernel's GB/s (algorithmic bytes / HIP-event time) of the large
-    workloads at their real sizes."""
+    workloads at their real sizes (``only``: one of them, in one storage)."""
     import gc
 
     from paper_2512_01027_amd import workloads as W
@@ -219,6 +219,10 @@ def workloads_leg(steps=100, warmup=10):
             ("head_on_collision_256x192x192", lambda st: W.config_head_on_collision(store=st), ("fp32", "fp16"))]
     out = {}
     for name, make, stores in runs:
+        if only is not None:
+            if name != only:
+                continue
+            stores = (only_store,)
         leg = {}
         cfg, fields, _ = make(stores[0])
         n = cfg["nx"] * cfg["ny"] * cfg["nz"]
@@ -272,7 +276,13 @@ def main():
     ap.add_argument("--no-workloads", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
+    ap.add_argument("--workload-only", default=None, metavar="NAME",
+                    help="only run one real-size workload of the workloads leg (for profiling)")
+    ap.add_argument("--store", default="fp32", help="storage of --workload-only")
     args = ap.parse_args()
+    if args.workload_only:
+        print(json.dumps({"workloads": workloads_leg(args.steps, args.warmup, args.workload_only, args.store)}))
+        return
     if args.copy_probe:
         print(json.dumps({"copy_probe_bytes": args.copy_probe << 20, "dispatches": 6,
                           "copy_GBs_read_plus_write": copy_bandwidth(args.copy_probe)}))
