@@ -44,7 +44,7 @@ METRIC = "coupled-lattice MLUPS, % HBM peak; p50/p99 case latency; FP16 vs FP32 
 COUNTERS = os.path.join(ROOT, "profiles", "galilean_droplet_128cube_hbm_counters.txt")
 # Algorithmic bytes per node of each kernel, 3D D3Q27 + D3Q19 (values per node
 # times their width, each read or written once): moments reads 46 populations
-# and writes phi, u*(3), S, M2(6); pressure reads u*(3), P, phi, S and writes
+# and writes phi, u*(3), P*, M2(6); pressure reads P*, u*(3), phi and writes
 # P; velocity reads P, u*(3), phi and writes u(3); collide reads phi, u(3),
 # M2(6), h(19) and writes 46 populations.  2-byte storage also reads the
 # previous-step phi in moments and collide (the h codec's reference) and the
@@ -61,7 +61,7 @@ def kernel_bytes(store_bytes, aux_bytes=4, pops=POP_VALUES_3D, dim=3):
     uref = dim * aux_bytes if store_bytes == 2 else 0
     return {
         "moments": pops * store_bytes + ref + uref + 11 * aux_bytes,
-        "pressure": 7 * aux_bytes,
+        "pressure": 6 * aux_bytes,
         "velocity": 8 * aux_bytes,
         "collide": 19 * store_bytes + ref + 10 * aux_bytes + pops * store_bytes,
     }
