@@ -422,14 +422,16 @@ struct Halo2 {
     }
 };
 
-// Fills a tile's 1-halo region in LDS from NV arrays (src[j]: node-indexed
-// array of CT).  store(k, cr, off, v) writes cell k from the NV values v of
-// its node, with the crossing flags and wall offsets of Halo1::cell.
+// Fills a tile's halo region in LDS (HR: Halo1, or Halo2 two nodes deep)
+// from NV arrays (src[j]: node-indexed array of CT).  store(k, cr, off, v)
+// writes cell k from the NV values v of its node, with the crossing flags and
+// wall offsets of HR::cell.
 //
 // A tile clear of walls, the open end and the block whose x range lies in the
 // grid takes the row path: each halo row's TX interior cells are read as
 // aligned 4-element vectors (tile origins and row pitches are multiples of 32
-// nodes), its two end cells one by one.  Only y and z wrap, once per row.
+// nodes), its D end cells on either side one by one.  Only y and z wrap, once
+// per row.
 //
 // Other tiles take the cell path: each thread takes the cells
 // k = threadIdx.x + 256 it, resolves all of them and issues all their loads
@@ -1459,8 +1461,8 @@ __global__ __launch_bounds__(256) void k_init(CaseTab cases, const int* hdr,
     CDesc& cs = *t.cs;
     const uint32_t N = (uint32_t)cs.N;
     const Phys<CT> ph = make_phys<CT>(cs);
-    // fixed trip count, fully unrolled: every halo load is issued before the
-    // first LDS write waits on one
+    // the halo cell by cell (initialisation runs once; the step kernels use
+    // halo_stage)
 #pragma unroll
     for (int it = 0; it < (R::N + 255) / 256; ++it) {
         const int k = threadIdx.x + 256 * it;
