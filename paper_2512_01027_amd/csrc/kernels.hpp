@@ -965,8 +965,9 @@ __global__ __launch_bounds__(256) void k_moments(CaseTab cases, const int* hdr, 
 //     P*.  Difference form: opposite links enter as
 //     (P(x - c) - P0) + (P(x + c) - P0) and as u*(x - c) - u*(x + c), each
 //     formed in the auxiliary type and so rounded relative to itself (the
-//     single differences exact for P within a factor 2); the sums over the
-//     links and the final combination are FP64.
+//     single differences exact for P within a factor 2); the sums within a
+//     shell are in the auxiliary type, the sum over shells and the final
+//     combination FP64.
 template <int LS, class AT, bool WALL, class R>
 __device__ __forceinline__ void pressure_tile(CDesc& cs, const TileCtx& t, AT* sP, AT* sGD, AT (*sJ)[R::N])
 {
@@ -1021,27 +1022,44 @@ __device__ __forceinline__ void pressure_tile(CDesc& cs, const TileCtx& t, AT* s
     const double rho = cs.rho_a + drho;
     const int cx = lx + 1, cy = ly + 1, cz = lz + HR::ZH;
     const AT P0 = sP[R::idx(cx, cy, cz)];
-    double sk = 0, du[3] = {0, 0, 0};
+    // The weight of a link depends on its shell alone, so the link terms are
+    // summed per shell, unweighted, in the auxiliary type (a handful of terms
+    // of one magnitude class, each a difference rounded relative to itself);
+    // the weighted sum over shells and the combination are FP64.
+    constexpr int NS = shell<G>(G::Q - 1) + 1;
+    AT sks[NS], sgs[NS], dus[3][NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        sks[s] = sgs[s] = 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) dus[a][s] = 0;
+    }
 #pragma unroll
     for (int i = 1; i < G::Q; i += 2) {  // pairs (i, i+1) are opposite
+        const int s = shell<G>(i);
         const int km = R::idx(cx - G::c(i, 0), cy - G::c(i, 1), cz - G::c(i, 2));
         const int kp = R::idx(cx + G::c(i, 0), cy + G::c(i, 1), cz + G::c(i, 2));
-        // the pair's two differences are added before widening (a second
-        // difference, rounded relative to itself); the sum over pairs is FP64
-        double dp = (double)((sP[km] - P0) + (sP[kp] - P0));
-        if (WALL) dp += rho * ((double)sGD[km] + (double)sGD[kp]);
-        sk += G::w(i) * dp;
+        // the pair's second difference of P
+        sks[s] += (sP[km] - P0) + (sP[kp] - P0);
+        if (WALL) sgs[s] += sGD[km] + sGD[kp];
 #pragma unroll
         for (int a = 0; a < DIMV; ++a) {
             if (G::c(i, a) == 0) continue;
-            const double d = G::w(i) * (double)(sJ[a][km] - sJ[a][kp]);
-            if (G::c(i, a) == 1) du[a] += d;
-            else du[a] -= d;
+            const AT d = sJ[a][km] - sJ[a][kp];
+            if (G::c(i, a) == 1) dus[a][s] += d;
+            else dus[a][s] -= d;
         }
     }
-    double su = 0;
+    double sk = 0, sg = 0, su = 0;
 #pragma unroll
-    for (int a = 0; a < DIMV; ++a) su += du[a];
+    for (int s = 0; s < NS; ++s) {
+        const double w = shell_w<G>(s);
+        sk += w * (double)sks[s];
+        if (WALL) sg += w * (double)sgs[s];
+#pragma unroll
+        for (int a = 0; a < DIMV; ++a) su += w * (double)dus[a][s];
+    }
+    if (WALL) sk += rho * sg;
     // rho_ref T (1 + omega) sum K = (1 + omega) rho_ref / rho * sum w dP = sk
     *at_node<AT>(cs.P[(t.step + 1) & 1], n) = (AT)((double)P0 + (sk + drho * su));
 }

@@ -57,6 +57,29 @@ struct D3Q19 {
     }
 };
 
+// Shell of link i: its number of non-zero components less one (axis links 0,
+// face diagonals 1, cube diagonals 2).  In D2Q9, D3Q19 and D3Q27 a link's
+// weight depends on its shell alone, which lets a weighted sum over links be
+// taken as a weighted sum over shells of plain sums.
+template <class G> __host__ __device__ constexpr int shell(int i)
+{
+    return (G::c(i, 0) != 0) + (G::c(i, 1) != 0) + (G::c(i, 2) != 0) - 1;
+}
+template <class G> __host__ __device__ constexpr double shell_w(int s)
+{
+    for (int i = 1; i < G::Q; ++i)
+        if (shell<G>(i) == s) return G::w(i);
+    return 0.0;
+}
+template <class G> constexpr bool weight_by_shell()
+{
+    for (int i = 1; i < G::Q; ++i)
+        if (G::w(i) != shell_w<G>(shell<G>(i))) return false;
+    return true;
+}
+static_assert(weight_by_shell<D2Q9>() && weight_by_shell<D3Q19>() && weight_by_shell<D3Q27>(),
+              "link weights depend on the shell alone");
+
 // Lattice sets: hydro lattice G, phase-field lattice H, dimension and the
 // workgroup tile.  Set 2: D2Q9 / D2Q9; set 3: D3Q27 / D3Q19; set 4: D3Q19 /
 // D3Q19 (the lattice the paper uses in 3D, Sec. II).  Tiles are 256 threads
