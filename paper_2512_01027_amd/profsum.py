@@ -2,6 +2,7 @@
 
     python -m paper_2512_01027_amd.profsum stats  <dir with *_kernel_stats.csv>
     python -m paper_2512_01027_amd.profsum hbm    <fetch dir> <write dir> <copy fetch dir> <copy write dir> <nodes>
+    python -m paper_2512_01027_amd.profsum issue  <dir of an SQ counter run> <trace dir>
 
 ``hbm`` turns FETCH_SIZE / WRITE_SIZE (KiB per dispatch) into HBM bytes per
 launch.  Each counter is scaled by what it reads for a plain device copy of
@@ -10,6 +11,12 @@ value), and the result is printed per kernel and per lattice node, followed
 by one ``traffic_json`` line that bench.py reads.  The line carries the
 SHA-256 of the kernel sources, so a summary taken before a kernel change is
 not used for the changed kernel.
+
+``issue`` turns SQ instruction counters (SQ_WAVES, SQ_INSTS_VALU,
+SQ_INSTS_LDS, SQ_INSTS_SALU) into instructions per wavefront and sets the
+VALU issue time they imply beside the kernel's average duration from a
+kernel trace.  Issue model: without packed FP32 a wave64 VALU instruction
+occupies its SIMD for 4 cycles; 1024 SIMDs (256 CUs x 4) at 2.4 GHz.
 """
 from __future__ import annotations
 
@@ -95,6 +102,30 @@ def hbm(fetch_dir, write_dir, cfetch_dir, cwrite_dir, nodes):
     return "\n".join(out)
 
 
+SIMDS, CLOCK_HZ, VALU_CYCLES = 1024, 2.4e9, 4
+
+
+def issue(sq_dir, trace_dir):
+    c = counters(sq_dir)
+    dur = {}
+    for r in csv.DictReader(open(_one(os.path.join(trace_dir, "**", "*kernel_stats.csv")))):
+        dur[short(r["Name"])] = float(r["AverageNs"]) / 1e3
+    out = ["kernel | waves/dispatch | VALU/wave | LDS/wave | SALU/wave | VALU issue us | avg us | issue share"]
+    for (k, name) in sorted(c):
+        if name != "SQ_WAVES" or not k.startswith("pulbm::") or c[(k, name)] <= 0:
+            continue
+        waves = c[(k, "SQ_WAVES")]
+        valu = c.get((k, "SQ_INSTS_VALU"), 0.0) / waves
+        lds = c.get((k, "SQ_INSTS_LDS"), 0.0) / waves
+        salu = c.get((k, "SQ_INSTS_SALU"), 0.0) / waves
+        t_issue = waves * valu * VALU_CYCLES / (SIMDS * CLOCK_HZ) * 1e6
+        d = dur.get(k)
+        share = f"{t_issue / d:.2f}" if d else "-"
+        out.append(f"{k} | {waves:.0f} | {valu:.0f} | {lds:.0f} | {salu:.0f} | {t_issue:.1f} | "
+                   f"{d if d is not None else float('nan'):.2f} | {share}")
+    return "\n".join(out)
+
+
 def load_traffic(path):
     """The traffic_json record of a committed summary, or None."""
     if not os.path.exists(path):
@@ -110,6 +141,8 @@ def main(argv):
         print(stats(argv[1]))
     elif len(argv) == 6 and argv[0] == "hbm":
         print(hbm(argv[1], argv[2], argv[3], argv[4], int(argv[5])))
+    elif len(argv) == 3 and argv[0] == "issue":
+        print(issue(argv[1], argv[2]))
     else:
         print(__doc__)
         return 2
