@@ -6,7 +6,7 @@
 //              phi = sum h, u* = sum g c, P* = rho_ref T sum g (the pressure
 //              the populations carry; the stored rest population lacks the
 //              previous P, which is added back) and M2 = sum g c c.
-//   k_pressure 1-halo LDS tile, FP64 sums: the pressure formula of Sec. II
+//   k_pressure 1-halo LDS tile, FP32 sums per shell, FP64 over shells: the pressure formula of Sec. II
 //              with K_i of P* and, in the omega term, u* at x - c_i.
 //   k_velocity 1-halo LDS tile: u = sum_i (g_i + K_i) c_i with K_i of the new
 //              pressure, i.e. u = u* - D P / rho.
