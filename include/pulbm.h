@@ -127,7 +127,12 @@ int pulbm_diagnostics(pulbm_case* c, pulbm_diag* d);
 
 /* Restart image (distributions in their storage precision, previous-step
  * pressure, phi and u, step count, parameters).  checkpoint_bytes gives the
- * size. */
+ * size.  pulbm_restore accepts only an image of a case with the same grid,
+ * lattices, storage, walls, open end (and p_top), block and collision; its
+ * section sizes must equal the case's and its step count be >= 0.  Anything
+ * else is PULBM_EINVAL before a byte is copied, and the case keeps its state.
+ * Fluid properties, body force and the delta-theta switch are the target
+ * case's own (the image's are ignored). */
 int pulbm_checkpoint_bytes(const pulbm_case* c, size_t* bytes);
 int pulbm_checkpoint(pulbm_case* c, void* host_buf, size_t bytes);
 int pulbm_restore(pulbm_case* c, const void* host_buf, size_t bytes);
@@ -139,6 +144,19 @@ void pulbm_destroy(pulbm_case* c);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* pulbm_last_error(void);
+
+/* -------------------------------------------------------------- measurement
+ * Bandwidth probe (not part of the method): copies `bytes` from device src to
+ * device dst `reps` times on the HIP stream (NULL = default) with a plain
+ * streaming kernel (16-byte vectors, 16 KiB per workgroup) and returns the
+ * average milliseconds per copy in *ms (HIP events; one untimed copy first).
+ * mode bit 0: non-temporal loads, bit 1: non-temporal stores.  bytes and
+ * both pointers must be multiples of 16 and the buffers must not overlap
+ * (PULBM_EINVAL otherwise).  The copy moves 2 * bytes of HBM traffic: it
+ * gives the attainable read + write rate that the step's traffic is set
+ * against.  Synchronises the stream. */
+int pulbm_stream_copy(void* dst, const void* src, size_t bytes, int32_t mode, int32_t reps, void* hip_stream,
+                      double* ms);
 
 /* ------------------------------------------------------------------ serving
  * A batch keeps many cases resident in one device arena (the budget,

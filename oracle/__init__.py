@@ -72,6 +72,7 @@ def load():
                                          C.c_double, dp, dp, dp, dp]
     lib.pulbm_oracle_stencil.argtypes = [vp, dp, dp, dp]
     lib.pulbm_oracle_num_threads.argtypes = []
+    lib.pulbm_oracle_set_num_threads.argtypes = [C.c_int]
     _lib = lib
     return lib
 
@@ -222,3 +223,9 @@ def node_eq(cfg: dict, phi, P, u, gradphi, lapphi, gradrho, G):
 
 def num_threads() -> int:
     return int(load().pulbm_oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the reference's node loops (its results do not depend on it)."""
+    if load().pulbm_oracle_set_num_threads(int(n)):
+        raise ValueError("thread count must be >= 1")

@@ -853,3 +853,12 @@ int pulbm_oracle_num_threads(void)
     return 1;
 #endif
 }
+
+int pulbm_oracle_set_num_threads(int n)
+{
+    if (n < 1) return -1;
+#ifdef _OPENMP
+    omp_set_num_threads(n);
+#endif
+    return 0;
+}

@@ -75,6 +75,8 @@ int  pulbm_oracle_node_eq(const pulbm_oracle_params* p, double phi, double P, co
  * case: grad[3*N] of an even field q[N], lap[N]. */
 int  pulbm_oracle_stencil(const pulbm_oracle_case* c, const double* q, double* grad, double* lap);
 int  pulbm_oracle_num_threads(void);
+/* Threads of the node loops from now on (>= 1); the arithmetic does not depend on it. */
+int  pulbm_oracle_set_num_threads(int n);
 
 #ifdef __cplusplus
 }

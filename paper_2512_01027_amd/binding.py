@@ -24,7 +24,7 @@ EXPORTS = [
     "pulbm_read_fields", "pulbm_diagnostics", "pulbm_checkpoint_bytes", "pulbm_checkpoint",
     "pulbm_restore", "pulbm_sync", "pulbm_steps_done", "pulbm_destroy", "pulbm_last_error",
     "pulbm_batch_create", "pulbm_batch_admit", "pulbm_batch_advance", "pulbm_batch_poll",
-    "pulbm_batch_take", "pulbm_batch_usage", "pulbm_batch_destroy",
+    "pulbm_batch_take", "pulbm_batch_usage", "pulbm_batch_destroy", "pulbm_stream_copy",
 ]
 
 
@@ -98,6 +98,7 @@ def load():
         "pulbm_batch_take": [vp, i32, dp, dp, dp],
         "pulbm_batch_usage": [vp, C.POINTER(sz), C.POINTER(i32)],
         "pulbm_batch_destroy": [vp],
+        "pulbm_stream_copy": [vp, vp, sz, i32, i32, vp, dp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -251,6 +252,14 @@ class Case:
     def restore(self, blob: bytes):
         buf = C.create_string_buffer(blob, len(blob))
         _check(self.lib.pulbm_restore(self._h, buf, len(blob)))
+
+
+def stream_copy(dst_ptr: int, src_ptr: int, nbytes: int, mode: int, reps: int, stream=None) -> float:
+    """Average milliseconds of a device-to-device streaming copy (bandwidth
+    probe; see pulbm_stream_copy)."""
+    ms = C.c_double()
+    _check(load().pulbm_stream_copy(dst_ptr, src_ptr, int(nbytes), int(mode), int(reps), stream, C.byref(ms)))
+    return ms.value
 
 
 class Batch:

@@ -6,8 +6,11 @@
 //              phi = sum h, u* = sum g c, P* = rho_ref T sum g (the pressure
 //              the populations carry; the stored rest population lacks the
 //              previous P, which is added back) and M2 = sum g c c.
-//   k_pressure 1-halo LDS tile, FP32 sums per shell, FP64 over shells: the pressure formula of Sec. II
-//              with K_i of P* and, in the omega term, u* at x - c_i.
+//   k_pressure 1-halo LDS tile: the pressure formula of Sec. II with K_i of
+//              P* and, in the omega term, u* at x - c_i.  Link terms are
+//              summed per shell in the auxiliary type (FP64 in FP64 storage,
+//              FP32 otherwise); the shell-weighted sum and the final
+//              combination are FP64.
 //   k_velocity 1-halo LDS tile: u = sum_i (g_i + K_i) c_i with K_i of the new
 //              pressure, i.e. u = u* - D P / rho.
 //   k_collide  1-halo LDS tile of phi and u: the isotropic central
@@ -99,13 +102,8 @@ using CaseTab = CaseDev* const*;
 // The grid is a multiple of 8.
 __device__ __forceinline__ int xcd_tile(int bid, int nblocks)
 {
-#ifdef PULBM_NO_XCD_REMAP
-    (void)nblocks;
-    return bid;
-#else
     const int per = nblocks >> 3;
     return (bid & 7) * per + (bid >> 3);
-#endif
 }
 
 __device__ __forceinline__ int find_case(const PULBM_CST int* tstart, int ncases, int tile)
@@ -295,14 +293,9 @@ __device__ __forceinline__ bool tile_at_wall(CDesc& cs, int ox, int oy, int oz)
 // was measured per storage width (bit 0: loads in k_moments, bit 1: loads in
 // k_collide, bit 2: stores in k_collide): 4- and 8-byte populations stream
 // their loads, 2-byte populations their stores.
-#ifndef PULBM_NT_WIDE
-#define PULBM_NT_WIDE 3
-#endif
-#ifndef PULBM_NT_HALF
-#define PULBM_NT_HALF 4
-#endif
 enum PopAccess { kLoadMoments = 1, kLoadCollide = 2, kStoreCollide = 4 };
-template <class S, int A> constexpr bool nt_access() { return ((sizeof(S) >= 4 ? PULBM_NT_WIDE : PULBM_NT_HALF) & A) != 0; }
+constexpr int kNtWide = kLoadMoments | kLoadCollide, kNtHalf = kStoreCollide;
+template <class S, int A> constexpr bool nt_access() { return ((sizeof(S) >= 4 ? kNtWide : kNtHalf) & A) != 0; }
 
 template <bool NT, class S> __device__ __forceinline__ S pop_ld(const PULBM_GLB S* p)
 {
@@ -1016,8 +1009,9 @@ __device__ __forceinline__ void pressure_tile(CDesc& cs, const TileCtx& t, AT* s
     }
     // omega = (rho - rho_ref) / rho_ref with omega_max = rho_w / rho_ref, so
     // (1 + omega) rho_ref / rho = 1 and omega rho_ref = rho - rho_ref, which
-    // weights the u* term by up to the density ratio: the sums and this
-    // combination are taken in FP64
+    // weights the u* term by up to the density ratio: the shell-weighted sums
+    // and this combination are taken in FP64 (the per-shell sums below are in
+    // the auxiliary type)
     const double drho = (double)clamp01(phi) * (cs.rho_w - cs.rho_a);
     const double rho = cs.rho_a + drho;
     const int cx = lx + 1, cy = ly + 1, cz = lz + HR::ZH;
@@ -1427,19 +1421,11 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
     }
 }
 
-// Occupancy target of the collision kernel in waves per SIMD (0 leaves the
-// register budget to the compiler).  Left alone the compiler takes ~175-195
-// VGPRs (2 waves); a budget of 168 (3 waves) costs a few dwords of spill and
-// hides enough more memory latency to run 10% (FP32) to 18% (FP16) faster;
-// 128 (4 waves) spills too much.
-#ifndef PULBM_COLLIDE_WAVES
-#define PULBM_COLLIDE_WAVES 3
-#endif
-#if PULBM_COLLIDE_WAVES > 0
-#define PULBM_COLLIDE_ATTR __attribute__((amdgpu_waves_per_eu(PULBM_COLLIDE_WAVES, PULBM_COLLIDE_WAVES)))
-#else
-#define PULBM_COLLIDE_ATTR
-#endif
+// Occupancy target of the collision kernel: 3 waves per SIMD.  Left alone
+// the compiler takes ~175-195 VGPRs (2 waves); a budget of 168 (3 waves)
+// costs a few dwords of spill and hides enough more memory latency to run
+// 10% (FP32) to 18% (FP16) faster; 128 (4 waves) spills too much.
+#define PULBM_COLLIDE_ATTR __attribute__((amdgpu_waves_per_eu(3, 3)))
 template <int LS, class S, bool BGK>
 __global__ __launch_bounds__(256) PULBM_COLLIDE_ATTR void k_collide(CaseTab cases, const int* hdr, int step_off)
 {

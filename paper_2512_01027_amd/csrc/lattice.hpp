@@ -95,18 +95,15 @@ template <> struct Model<2> {
     static constexpr int DIM = 2;
     static constexpr int TX = 64, TY = 4, TZ = 1;
 };
-#ifndef PULBM_TILE3
-#define PULBM_TILE3 64, 2, 2
-#endif
-template <int X, int Y, int Z> struct Tile3 {
-    static constexpr int TX = X, TY = Y, TZ = Z;
+struct Tile3 {
+    static constexpr int TX = 64, TY = 2, TZ = 2;
 };
-template <> struct Model<3> : Tile3<PULBM_TILE3> {
+template <> struct Model<3> : Tile3 {
     using G = D3Q27;
     using H = D3Q19;
     static constexpr int DIM = 3;
 };
-template <> struct Model<4> : Tile3<PULBM_TILE3> {
+template <> struct Model<4> : Tile3 {
     using G = D3Q19;
     using H = D3Q19;
     static constexpr int DIM = 3;

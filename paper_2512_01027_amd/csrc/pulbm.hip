@@ -429,13 +429,12 @@ extern "C" int pulbm_init_fields(pulbm_case* c, const double* phi, const double*
     // stage the FP64 inputs in the case's own scratch fields (u*, P*, M2,
     // U[0]), which k_init does not touch (it writes U[1]); no allocation on
     // this path
+    // (u*, P*, M2 and U[0] hold at least (dim + 1 + 3 + dim) * N auxiliary
+    // values of 4 or 8 bytes, which covers (2 + dim) * N doubles whenever
+    // dim <= 3; checked anyway)
     const size_t bytes = (2 + (size_t)dim) * N * sizeof(double);
     double* tmp = (double*)(c->base + c->L.J);
-    bool own_tmp = false;
-    if (bytes > c->L.U1 - c->L.J) {
-        HIPC(hipMalloc((void**)&tmp, bytes));
-        own_tmp = true;
-    }
+    if (bytes > c->L.U1 - c->L.J) return fail(PULBM_EDEVICE, "internal: init staging does not fit the scratch fields");
     // compact host rows of nx padded to rows of sx on the host (the padding is
     // never read), then one contiguous copy
     const size_t sx = (size_t)c->h.sx;
@@ -452,7 +451,6 @@ extern "C" int pulbm_init_fields(pulbm_case* c, const double* phi, const double*
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    if (own_tmp) (void)hipFree(tmp);
     if (e != hipSuccess) return fail(PULBM_EDEVICE, "init failed: %s", hipGetErrorString(e));
     c->step = 0;
     c->ready = true;
@@ -633,8 +631,22 @@ extern "C" int pulbm_restore(pulbm_case* c, const void* buf, size_t bytes)
     const pulbm_params& q = hd.p;
     const pulbm_params& p = c->p;
     if (q.dim != p.dim || q.nx != p.nx || q.ny != p.ny || q.nz != p.nz || q.store != p.store ||
-        q.q_hydro != p.q_hydro || q.q_phase != p.q_phase)
+        hd.store != p.store || q.q_hydro != p.q_hydro || q.q_phase != p.q_phase)
         return fail(PULBM_EINVAL, "restart image is for a different grid or precision");
+    // the boundaries and the collision shape the stored state (bounce-back
+    // slots, block nodes, the rest population of BGK), so they must match too;
+    // fluid properties and body force are taken from the target case
+    bool same_geometry = q.collision == p.collision && q.p_top == p.p_top;
+    for (int a = 0; a < 3; ++a)
+        same_geometry = same_geometry && q.wall[a] == p.wall[a] && q.block_lo[a] == p.block_lo[a] &&
+                        q.block_hi[a] == p.block_hi[a];
+    if (!same_geometry) return fail(PULBM_EINVAL, "restart image is for different boundaries or collision");
+    // section sizes are checked against the case, never trusted from the image
+    const size_t N = (size_t)c->h.N, sb = store_bytes(p.store), ab = aux_bytes(p.store);
+    if (hd.h_bytes != (uint64_t)p.q_phase * N * sb || hd.g_bytes != (uint64_t)p.q_hydro * N * sb ||
+        hd.P_bytes != (uint64_t)N * ab)
+        return fail(PULBM_EINVAL, "restart image section sizes do not match the case");
+    if (hd.step < 0) return fail(PULBM_EINVAL, "restart image has a negative step count");
     size_t need = 0;
     pulbm_checkpoint_bytes(c, &need);
     if (bytes < need) return fail(PULBM_EINVAL, "restart image too short");
@@ -667,6 +679,86 @@ extern "C" int pulbm_sync(pulbm_case* c)
 }
 
 extern "C" int64_t pulbm_steps_done(const pulbm_case* c) { return c ? c->step : -1; }
+
+// ============================================================= measurement
+
+namespace {
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Streaming copy: each block moves 1024 16-byte vectors (16 KiB), every load
+// of a thread issued before its first store.  NTL / NTS: non-temporal loads /
+// stores, the access hints the step kernels choose per storage width.
+template <bool NTL, bool NTS>
+__global__ __launch_bounds__(256) void k_stream_copy(const u32x4* __restrict__ src, u32x4* __restrict__ dst,
+                                                     uint64_t n16)
+{
+    const uint64_t base = (uint64_t)blockIdx.x * 1024 + threadIdx.x;
+    u32x4 v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint64_t i = base + 256 * k;
+        if (i < n16) {
+            if constexpr (NTL) v[k] = __builtin_nontemporal_load(src + i);
+            else v[k] = src[i];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint64_t i = base + 256 * k;
+        if (i < n16) {
+            if constexpr (NTS) __builtin_nontemporal_store(v[k], dst + i);
+            else dst[i] = v[k];
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" int pulbm_stream_copy(void* dst, const void* src, size_t bytes, int32_t mode, int32_t reps,
+                                 void* hip_stream, double* ms)
+{
+    if (!dst || !src || !ms) return fail(PULBM_EINVAL, "NULL argument");
+    if (bytes == 0 || bytes % 16 || ((uintptr_t)dst | (uintptr_t)src) % 16)
+        return fail(PULBM_EINVAL, "bytes and both pointers must be non-zero multiples of 16");
+    if (mode < 0 || mode > 3) return fail(PULBM_EINVAL, "mode must be 0..3");
+    if (reps < 1) return fail(PULBM_EINVAL, "reps must be >= 1");
+    const char* s = (const char*)src;
+    const char* d = (const char*)dst;
+    if (s < d + bytes && d < s + bytes) return fail(PULBM_EINVAL, "source and destination overlap");
+    hipStream_t st = (hipStream_t)hip_stream;
+    const uint64_t n16 = bytes / 16;
+    const uint64_t blocks = (n16 + 1023) / 1024;
+    if (blocks > 0x7fffffffull) return fail(PULBM_EINVAL, "copy too large");
+    const u32x4* a = (const u32x4*)src;
+    u32x4* b = (u32x4*)dst;
+    auto go = [&]() {
+        const dim3 grid((unsigned)blocks), block(256);
+        switch (mode) {
+            case 0: hipLaunchKernelGGL((k_stream_copy<false, false>), grid, block, 0, st, a, b, n16); break;
+            case 1: hipLaunchKernelGGL((k_stream_copy<true, false>), grid, block, 0, st, a, b, n16); break;
+            case 2: hipLaunchKernelGGL((k_stream_copy<false, true>), grid, block, 0, st, a, b, n16); break;
+            default: hipLaunchKernelGGL((k_stream_copy<true, true>), grid, block, 0, st, a, b, n16); break;
+        }
+    };
+    go();  // warm
+    HIPC(hipGetLastError());
+    hipEvent_t e0, e1;
+    HIPC(hipEventCreate(&e0));
+    HIPC(hipEventCreate(&e1));
+    (void)hipEventRecord(e0, st);
+    for (int r = 0; r < reps; ++r) go();
+    (void)hipEventRecord(e1, st);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float t = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return fail(PULBM_EDEVICE, "stream copy failed: %s", hipGetErrorString(e));
+    *ms = (double)t / reps;
+    return PULBM_OK;
+}
 
 // ============================================================= serving batch
 

@@ -225,14 +225,12 @@ def config_dam_break_2d(nx=512, ny=256, store="fp32", nu_light=0.05):
 # per node, water column H = 0.55 m high, block 0.161 x 0.403 x 0.161 m with
 # its near face 0.744 m from the left end, centred across; water 999.10 and
 # air 1.225 kg/m^3, nu 1.139e-6 and 1.461e-5 m^2/s, sigma 0.072 N/m; the
-# characteristic velocity sqrt(2 g H) is 0.0289 in lattice units.  Sensors
-# (centred across): water heights at 0.496, 0.992 and 2.638 m from the left
-# end; pressures on the block at heights 0.021 and 0.101 m on its face toward
-# the water and on its top 0.021 m from that face.
+# characteristic velocity sqrt(2 g H) is 0.0289 in lattice units.  Only the
+# geometry and the fluid parameters are used: the experiment's sensor records
+# are not part of this workload.
 DAM = {"L": 3.22, "B": 1.0, "Hbox": 1.0, "dx": 5.5e-3, "H": 0.55, "block": (0.161, 0.403, 0.161),
        "block_x": 0.744, "rho_w": 999.10, "rho_a": 1.225, "nu_w": 1.139e-6, "nu_a": 1.461e-5,
-       "sigma": 0.072, "U": 0.0289, "heights": (0.496, 0.992, 2.638), "p_face": (0.021, 0.101),
-       "p_top_from_face": 0.021}
+       "sigma": 0.072, "U": 0.0289}
 
 
 def config_dam_break_block(store="fp16", nu_water=2e-3, column=0.25, q_hydro=27):
@@ -245,7 +243,8 @@ def config_dam_break_block(store="fp16", nu_water=2e-3, column=0.25, q_hydro=27)
     step is stable at, so nu_water is a parameter (2e-3: tau = 0.506).  The
     paper does not give the water column's length: it is column x the
     container length, at the end away from the block.
-    Returns cfg, fields and a dict of sensor positions (node indices)."""
+    Returns cfg, fields and a dict with the block's position and the steps
+    of one physical second."""
     d = DAM
     dx = d["dx"]
     nx, ny, nz = (int(round(v / dx)) for v in (d["L"], d["B"], d["Hbox"]))
@@ -278,13 +277,8 @@ def config_dam_break_block(store="fp16", nu_water=2e-3, column=0.25, q_hydro=27)
     blk = (slice(0, bz), slice(y0, y0 + by), slice(x0, x0 + bx))
     phi[blk] = 0.0
     P[blk] = 0.0
-    face = x0 + bx  # first fluid node past the block's face toward the water
-    sensors = {"heights_x": [int(round(v / dx)) for v in d["heights"]], "y": ny // 2,
-               "P1": (face, ny // 2, int(round(d["p_face"][0] / dx))),
-               "P3": (face, ny // 2, int(round(d["p_face"][1] / dx))),
-               "P5": (face - 1 - int(round(d["p_top_from_face"] / dx)), ny // 2, bz),
-               "steps_per_second": 1.0 / dt, "g": g}
-    return cfg, (phi, P, u), sensors
+    info = {"block_face_x": x0 + bx, "column_start_x": xc, "steps_per_second": 1.0 / dt, "g": g}
+    return cfg, (phi, P, u), info
 
 
 # Table I of Sec. III.D: surrounding fluid density, dynamic viscosities of

@@ -47,7 +47,7 @@ def lib():
 
 def test_header_matches_exports_and_binding(lib):
     decl = _declared()
-    assert len(decl) == 21
+    assert len(decl) == 22
     assert decl == _exported()
     assert decl == set(B.EXPORTS)
     for name in decl:
@@ -153,6 +153,22 @@ def test_null_handles(lib):
     assert lib.pulbm_batch_create(0, 9, 4, None, C.byref(out)) == B.EINVAL
     assert lib.pulbm_batch_create(0, 2, 0, None, C.byref(out)) == B.EINVAL
     assert not out.value
+
+
+def test_stream_copy_argument_checks(lib):
+    """The bandwidth probe refuses bad arguments on the host, before any HIP
+    call (the addresses below are never dereferenced)."""
+    ms = C.c_double()
+    a, b = 1 << 20, 1 << 24
+    assert lib.pulbm_stream_copy(None, b, 4096, 0, 1, None, C.byref(ms)) == B.EINVAL
+    assert lib.pulbm_stream_copy(a, b, 4096, 0, 1, None, None) == B.EINVAL
+    assert lib.pulbm_stream_copy(a, b, 4095, 0, 1, None, C.byref(ms)) == B.EINVAL
+    assert lib.pulbm_stream_copy(a + 8, b, 4096, 0, 1, None, C.byref(ms)) == B.EINVAL
+    assert lib.pulbm_stream_copy(a, b, 0, 0, 1, None, C.byref(ms)) == B.EINVAL
+    assert lib.pulbm_stream_copy(a, b, 4096, 4, 1, None, C.byref(ms)) == B.EINVAL
+    assert lib.pulbm_stream_copy(a, b, 4096, 0, 0, None, C.byref(ms)) == B.EINVAL
+    assert lib.pulbm_stream_copy(a, a + 2048, 4096, 0, 1, None, C.byref(ms)) == B.EINVAL
+    assert "overlap" in lib.pulbm_last_error().decode()
 
 
 def test_last_error_is_thread_local(lib):
