@@ -12,7 +12,7 @@ Printed as one JSON line:
   value          MLUPS of the whole step (wall clock over --steps steps)
   roofline       the step (its four kernels together): the state bytes per
                  node update of the storage mode (216 B in FP16: 46 two-byte
-                 populations and the FP32 pressure, each read and written
+                 populations and the FP32 P and u, each read and written
                  once) x nodes / the summed average HIP-event time of the four
                  kernels, against 8 TB/s; traffic = HBM bytes per step from
                  the committed rocprofv3 counter summary when it was taken on
@@ -86,9 +86,13 @@ def kernel_bytes(store_bytes, aux_bytes=4, pops=46, dim=3, q_phase=19):
     }
 
 
-def state_bytes(store_bytes, aux_bytes=4, pops=46):
-    """Read and write of the state (the populations and the pressure) once."""
-    return 2 * (pops * store_bytes + aux_bytes)
+def state_bytes(store_bytes, aux_bytes=4, pops=46, dim=3):
+    """Algorithmic bytes of one node update: the state read and written once.
+    The state is the populations and the macroscopic P and u carried from one
+    step to the next (the pressure is carried next to the populations, and the
+    velocity is the reference of the 2-byte codecs): 400 B in 3D FP32 storage,
+    216 B in FP16 or BF16 storage (P and u FP32)."""
+    return 2 * (pops * store_bytes + (1 + dim) * aux_bytes)
 
 
 def run_gpu(cfg, fields, steps, warmup, warm_fn=None):

@@ -51,6 +51,7 @@ def short(name: str) -> str:
     if m:
         flag = "" if m.group(4) is None else (", true" if m.group(4) == "1" else ", false")
         name = f"pulbm::{m.group(1)}<{m.group(2)}, {_TYPES[m.group(3)]}{flag}>"
+    name = name.replace("(anonymous namespace)::", "")
     name = re.sub(r"\(.*", "", name)
     return name.replace("void ", "")
 

@@ -21,8 +21,10 @@ def test_fp32_d3q27_bytes_per_node():
     # collide: h(19), phi, u(3), M2(6) in, 46 populations out
     assert kb["collide"] == 19 * 4 + 10 * 4 + 46 * 4 == 300
     assert sum(kb.values()) == 584
-    # state: populations and P, read and written once
-    assert bench.state_bytes(4) == 2 * (46 * 4 + 4) == 376
+    # state: populations, P and u, read and written once
+    assert bench.state_bytes(4) == 2 * (46 * 4 + 4 * 4) == 400
+    assert bench.state_bytes(2) == 2 * (46 * 2 + 4 * 4) == 216
+    assert bench.state_bytes(8, aux_bytes=8, pops=18, dim=2) == 2 * (18 * 8 + 3 * 8) == 336
 
 
 def test_fp16_bytes_per_node():
