@@ -35,6 +35,10 @@ by side on the same inputs:
              previous P in both formulas, the omega term of the previous u.
   "u_first"  u first, from K_i of the previous P; then P from K_i of the
              previous P and the omega term of that new u.
+
+``leave_out`` names terms of the method to drop, for diagnostic runs only
+(never a reading): "stress_density" (the w_i c_l sigma_lm d_m rho / (rho^2 T)
+term of g^eq), "bulk" (B = 0), "omega" (the omega term of the pressure).
 """
 from __future__ import annotations
 
@@ -70,9 +74,13 @@ def velocity_set(dim, q):
 class Twin:
     """One case, held as whole-grid arrays (z, y, x)."""
 
-    def __init__(self, cfg: dict, reading: str = "pstar"):
+    def __init__(self, cfg: dict, reading: str = "pstar", leave_out=()):
         if reading not in READINGS:
             raise ValueError(f"unknown reading {reading!r}")
+        unknown = set(leave_out) - {"stress_density", "bulk", "omega"}
+        if unknown:
+            raise ValueError(f"unknown terms {sorted(unknown)}")
+        self.leave_out = frozenset(leave_out)
         if cfg.get("block") or any(int(w) == 2 for w in cfg.get("wall", (0, 0, 0))):
             raise ValueError("the twin covers periodic axes and no-slip walls only")
         self.reading = reading
@@ -210,6 +218,8 @@ class Twin:
             om = self._omega_sum(self.ulag, "u")
         else:
             om = self._omega_sum(J, "ustar")
+        if "omega" in self.leave_out:
+            om = 0.0
         P = self.ra * T * (gsum + (1.0 + omega) * sum(K)) + omega * self.ra * om
         if r != "u_first":
             Ku = K if r == "lag_both" else self._k_terms(P, rho)
@@ -256,13 +266,14 @@ class Twin:
             for b in range(dim):
                 sig[a, b] = rho * nu * (G[a, b] + G[b, a])
             sig[a, a] += rho * (2.0 / 3.0) * (self.lam - nu) * div
-        B = (2.0 / 3.0) * (nu - self.lam) + T / 2.0
+        B = 0.0 if "bulk" in self.leave_out else (2.0 / 3.0) * (nu - self.lam) + T / 2.0
         geq = np.empty((len(self.cG),) + self.shape)
         for i, (ci, wi) in enumerate(zip(self.cG, self.wG)):
             rest = 1.0 if not ci.any() else 0.0
             cu = sum(ci[a] * u[a] for a in range(dim))
             cF = sum(ci[a] * F[a] for a in range(dim))
-            csd = sum(ci[l] * sig[l, m] * grho[m] for l in range(dim) for m in range(dim))
+            csd = 0.0 if "stress_density" in self.leave_out else sum(
+                ci[l] * sig[l, m] * grho[m] for l in range(dim) for m in range(dim))
             gam = wi * (1.0 + cu / T + cu * cu / (2 * T * T) - u2 / (2 * T))
             geq[i] = (P / (self.ra * T) * rest + gam - wi + wi * cF / (rho * T)
                       + B * (wi - rest) / T * div + wi * csd / (rho * rho * T))

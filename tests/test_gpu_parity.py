@@ -102,6 +102,18 @@ def test_degenerate_thin_grids(shape):
     _compare(g.read_fields(), o.read_fields(), TOL64, f"thin {shape}")
 
 
+def _record(name, rec):
+    """One JSON line of a test's achieved errors in the results directory."""
+    import json
+    import os
+
+    out = os.environ.get("PULBM_RESULTS_DIR",
+                         os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "results"))
+    os.makedirs(out, exist_ok=True)
+    with open(os.path.join(out, "parity.jsonl"), "a") as f:
+        f.write(json.dumps({"test": name, "records": rec}) + "\n")
+
+
 def _errs(a, b, p_scale, u_scale):
     """Max differences relative to the field scale: phi's range, the Laplace
     pressure sigma/R for P (P0 = 0, so P itself starts at zero), and
@@ -131,7 +143,8 @@ def test_static_droplet_2d_config_full_run():
     o2 = oracle.OracleCase(cfg)
     o2.init_fields(f[0] * (1 + 1e-15 * rng.standard_normal(f[0].shape)), f[1], f[2])
     done = 0
-    for s in (1, 3, 100, steps):
+    rec = []
+    for s in (1, 3, 100, 1000, steps):
         g.step(s - done)
         o.step(s - done)
         o2.step(s - done)
@@ -140,8 +153,11 @@ def test_static_droplet_2d_config_full_run():
         eg = _errs(g.read_fields(), ref, 0.01 / 16, 1e-6)
         ee = _errs(o2.read_fields(), ref, 0.01 / 16, 1e-6)
         print(f"step {s}: gpu-ref {eg}, ref-envelope {ee}", flush=True)
+        rec.append({"step": s, **{f"{nm}_err": float(f"{eg[k]:.3e}") for k, nm in enumerate(("phi", "P", "u"))},
+                    **{f"{nm}_envelope": float(f"{ee[k]:.3e}") for k, nm in enumerate(("phi", "P", "u"))}})
         for k in range(3):
             assert eg[k] < max(1e-10, 3 * ee[k]), (s, k, eg, ee)
+    _record("static_droplet_2d_fp64_2000_steps", rec)
     gr = g.read_fields()
     dg, do = g.diagnostics(), o.diagnostics()
     m0 = f[0].sum()

@@ -9,10 +9,15 @@
   granularity;
 - admission is bounded by the memory budget and the slot count (EAGAIN), and
   a taken case frees both.
+- the cases of an FP64 batch (2D and 3D, periodic and walled, filter and
+  BGK collision, D3Q19 hydro) agree with the FP64 CPU reference element by
+  element within 1e-10, and the cases of an FP16 batch with it within the
+  FP16 storage tolerance of the precision tests.
 """
 import numpy as np
 import pytest
 
+import oracle
 from paper_2512_01027_amd import binding as B
 from paper_2512_01027_amd import workloads as W
 
@@ -119,3 +124,78 @@ def test_admission_budget_and_slots():
         bt.admit(dict(cfg, store="fp32"), *f, n)
     assert e.value.code == B.EINVAL
     bt.close()
+
+
+def _smooth_fields(cfg, seed, R):
+    """A droplet with smooth seeded perturbations of phi, u and P: |grad phi|
+    stays well above the normal's epsilon everywhere, so FP64 implementations
+    agree to rounding."""
+    dim = cfg["dim"]
+    c = (cfg["nx"] * 0.47, cfg["ny"] * 0.53, cfg["nz"] * 0.45)
+    phi, P, u = W.droplet(cfg, R, center=c)
+    phi = np.clip(phi + W.random_smooth(cfg, seed, amp=0.02), 0, 1)
+    for a in range(dim):
+        u[a] += W.random_smooth(cfg, seed + 1 + a, amp=0.01)
+    P += W.random_smooth(cfg, seed + 9, amp=1e-3)
+    return phi, P, u
+
+
+def test_batch_fp64_matches_reference():
+    cases = [
+        (W.base_case(2, 70, 37, sigma=0.01, nu_heavy=0.05, nu_light=0.15, store="fp64"), 8.0, 31),
+        (W.base_case(3, 33, 9, 8, wall=(0, 0, 1), gravity=(0.0, 0.0, -1e-5), nu_heavy=0.05, nu_light=0.15,
+                     store="fp64"), 2.5, 24),
+        (W.base_case(3, 20, 7, 9, wall=(1, 1, 1), gravity=(1e-6, 2e-6, -1e-5), nu_heavy=0.1, nu_light=0.1,
+                     collision="bgk", store="fp64"), 2.0, 17),
+        (W.base_case(3, 37, 10, 7, q_hydro=19, sigma=0.01, nu_heavy=0.05, nu_light=0.15, store="fp64"), 2.0, 28),
+    ]
+    bt = B.Batch(1 << 30, store="fp64", max_slots=8)
+    slots, fields = {}, []
+    for k, (cfg, R, n) in enumerate(cases):
+        f = _smooth_fields(cfg, 5 + k, R)
+        fields.append(f)
+        slots[bt.admit(cfg, *f, n)] = k
+    got = {}
+    while len(got) < len(cases):
+        bt.advance(5)
+        for s in bt.poll():
+            got[slots[s]] = bt.take(s)
+    bt.close()
+    for k, (cfg, R, n) in enumerate(cases):
+        o = oracle.OracleCase(cfg)
+        o.init_fields(*fields[k])
+        o.step(n)
+        ref = o.read_fields()
+        for name, a, b in zip(("phi", "P", "u"), got[k], ref):
+            scale = max(np.abs(b - (b.mean() if name == "P" else 0.0)).max(), 1e-12)
+            err = np.abs(a - b).max() / scale
+            print(f"case {k} {name}: {err:.2e}", flush=True)
+            assert err < 1e-10, (k, name, err)
+
+
+def test_batch_fp16_within_storage_tolerance():
+    """Two cases of the FP16 precision test served together in one FP16
+    batch: the same gates against the FP64 reference as when run alone."""
+    import test_gpu_precision as TP
+
+    names = ["galilean_droplet_3d", "rising_bubble_2d"]
+    steps = 200
+    cases = TP._cases()
+    bt = B.Batch(1 << 30, store="fp16", max_slots=4)
+    slots = {}
+    for nm in names:
+        cfg, f = cases[nm]
+        slots[bt.admit(dict(cfg, store="fp16"), *f, steps)] = nm
+    got = {}
+    while len(got) < len(names):
+        bt.advance(16)
+        for s in bt.poll():
+            got[slots[s]] = bt.take(s)
+    bt.close()
+    for nm in names:
+        cfg, _ = cases[nm]
+        e = TP.errors(got[nm], TP._reference(nm, steps), cfg["rho_heavy"])
+        ok, bound = TP._gate(nm, "fp16", e, TP._envelope(nm, steps))
+        print(nm, e, flush=True)
+        assert ok, (nm, e, bound)
+

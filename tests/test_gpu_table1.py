@@ -48,10 +48,18 @@ def test_table1_fp64_parity(case):
     p.step(steps)
     got, ref, per = g.read_fields(), o.read_fields(), p.read_fields()
     scale = [1.0, max(np.abs(ref[1] - ref[1].mean()).max(), 1e-12), max(np.abs(ref[2]).max(), 1e-12)]
+    rec = {"test": f"table1_case{case}_fp64_parity", "steps": steps}
+    ok = []
     for k, name in enumerate(("phi", "P", "u")):
         err = np.abs(got[k] - ref[k]).max() / scale[k]
         env = np.abs(per[k] - ref[k]).max() / scale[k]
         print(name, f"gpu {err:.2e} envelope {env:.2e}", flush=True)
+        rec[f"{name}_err"], rec[f"{name}_envelope"] = float(f"{err:.3e}"), float(f"{env:.3e}")
+        ok.append((name, err, env))
+    os.makedirs(OUT, exist_ok=True)
+    with open(os.path.join(OUT, "parity.jsonl"), "a") as fh:
+        fh.write(json.dumps(rec) + "\n")
+    for name, err, env in ok:
         assert err <= max(1e-10, 3.0 * env), (name, err, env)
 
 
