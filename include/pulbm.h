@@ -121,6 +121,18 @@ int pulbm_step_timed(pulbm_case* c, int64_t nsteps, double* ms);
  * the current distributions without changing them.  Synchronises. */
 int pulbm_read_fields(pulbm_case* c, double* phi, double* P, double* u);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): the same phi, P, u as
+ * pulbm_read_fields (bit for bit), read back without any host or device
+ * allocation.  The compact FP64 fields are staged in a fixed device array of
+ * the library (64 MiB on each GPU it runs on, held until the process ends),
+ * so (2 + dim) * nx * ny * nz doubles must fit it: at most 1,677,721 nodes in
+ * 3D, 2,097,152 in 2D (PULBM_EINVAL otherwise, before any GPU work).  Calls
+ * on one GPU share that array; within a process they are serialised by a
+ * lock, so calls overlapping from several threads wait for each other.
+ * Synchronises the case's stream. */
+int pulbm_read_fields_noalloc(pulbm_case* c, double* phi, double* P, double* u);
+
 /* Conservation diagnostics of the current state (FP64 wave reductions).
  * Returns PULBM_EDIVERGED (with *d filled) if any value is non-finite. */
 int pulbm_diagnostics(pulbm_case* c, pulbm_diag* d);

@@ -25,6 +25,7 @@ EXPORTS = [
     "pulbm_restore", "pulbm_sync", "pulbm_steps_done", "pulbm_destroy", "pulbm_last_error",
     "pulbm_batch_create", "pulbm_batch_admit", "pulbm_batch_advance", "pulbm_batch_poll",
     "pulbm_batch_take", "pulbm_batch_usage", "pulbm_batch_destroy", "pulbm_stream_copy",
+    "pulbm_read_fields_noalloc",
 ]
 
 
@@ -83,6 +84,7 @@ def load():
         "pulbm_step": [vp, i64],
         "pulbm_step_timed": [vp, i64, dp],
         "pulbm_read_fields": [vp, dp, dp, dp],
+        "pulbm_read_fields_noalloc": [vp, dp, dp, dp],
         "pulbm_diagnostics": [vp, C.POINTER(Diag)],
         "pulbm_checkpoint_bytes": [vp, C.POINTER(sz)],
         "pulbm_checkpoint": [vp, vp, sz],
@@ -230,6 +232,19 @@ class Case:
         P = np.empty(self.N)
         u = np.empty(self.dim * self.N)
         _check(self.lib.pulbm_read_fields(self._h, _dp(phi), _dp(P), _dp(u)))
+        return (phi.reshape(self.shape), P.reshape(self.shape),
+                u.reshape((self.dim,) + self.shape))
+
+    def read_fields_noalloc(self, phi=None, P=None, u=None):
+        """As read_fields, through the allocation-free entry point; the
+        caller may pass the output arrays (FP64, C-contiguous)."""
+        phi = np.empty(self.N) if phi is None else phi
+        P = np.empty(self.N) if P is None else P
+        u = np.empty(self.dim * self.N) if u is None else u
+        for a, n in ((phi, self.N), (P, self.N), (u, self.dim * self.N)):
+            if a.dtype != np.float64 or not a.flags["C_CONTIGUOUS"] or a.size != n:
+                raise ValueError("output arrays must be C-contiguous FP64 of the case's sizes")
+        _check(self.lib.pulbm_read_fields_noalloc(self._h, _dp(phi), _dp(P), _dp(u)))
         return (phi.reshape(self.shape), P.reshape(self.shape),
                 u.reshape((self.dim,) + self.shape))
 

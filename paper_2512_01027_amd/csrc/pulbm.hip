@@ -12,6 +12,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -180,6 +181,7 @@ struct pulbm_case {
     int ntiles = 0;
     int64_t step = 0;
     bool ready = false;
+    int device = 0;           // device current at pulbm_create
 };
 
 // ------------------------------------------------------------ dispatch
@@ -327,6 +329,10 @@ extern "C" int pulbm_create(const pulbm_params* p, void* dev_arena, size_t arena
     c->p = *p;
     c->stream = (hipStream_t)hip_stream;
     c->L = make_layout(*p);
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return fail(PULBM_EDEVICE, "hipGetDevice failed");
+    }
     if (dev_arena) {
         if (arena_bytes < c->L.total) {
             delete c;
@@ -535,6 +541,104 @@ extern "C" int pulbm_read_fields(pulbm_case* c, double* phi, double* P, double* 
     if ((rc = fetch(c, c->h.P[(c->step + 1) & 1], P, 1))) return rc;
     if ((rc = fetch(c, c->h.U[c->step & 1], u, c->p.dim))) return rc;
     return PULBM_OK;
+}
+
+// ============================================= allocation-free read-back
+
+namespace {
+
+// Device staging of pulbm_read_fields_noalloc: the compact FP64 phi, P and u
+// of one case.  Each GPU the library runs on holds its own copy until the
+// process ends; host code reaches it only through the address that
+// hipGetSymbolAddress gives on that device (scratch_ptr).
+constexpr size_t kScratchBytes = size_t(64) << 20;
+__device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
+constexpr int kMaxDevices = 64;
+struct ScratchDev {
+    std::mutex lock;       // one call at a time uses a device's array
+    void* ptr = nullptr;   // its device address, once looked up
+};
+ScratchDev g_scratch[kMaxDevices];
+
+// Device address of `scratch` on device dev (which must be current).
+int scratch_ptr(int dev, void** out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return fail(PULBM_EDEVICE, "device %d out of range", dev);
+    ScratchDev& sd = g_scratch[dev];
+    if (!sd.ptr) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress((void**)&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(PULBM_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        sd.ptr = p;
+    }
+    *out = sd.ptr;
+    return PULBM_OK;
+}
+
+// Compact FP64 copies of phi, P and the dim velocity components (padded rows
+// of sx nodes in the auxiliary type -> rows of nx doubles), field after field.
+template <class AT>
+__global__ __launch_bounds__(256) void k_pack_fields(const AT* __restrict__ phi, const AT* __restrict__ P,
+                                                     const AT* __restrict__ U, int64_t N, int nx, int sx,
+                                                     int64_t nc, int comps, double* __restrict__ out)
+{
+    const int64_t total = nc * comps;
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < total; k += (int64_t)gridDim.x * 256) {
+        const int64_t f = k / nc, n = k - f * nc;
+        const int64_t m = (n % nx) + (int64_t)sx * (n / nx);
+        const AT* src = f == 0 ? phi : (f == 1 ? P : U + (f - 2) * N);
+        out[k] = (double)src[m];
+    }
+}
+
+}  // namespace
+
+extern "C" int pulbm_read_fields_noalloc(pulbm_case* c, double* phi, double* P, double* u)
+{
+    if (!c || !phi || !P || !u) return fail(PULBM_EINVAL, "NULL argument");
+    if (!c->ready) return fail(PULBM_ESTATE, "read before init");
+    const int dim = c->p.dim, comps = 2 + dim;
+    const size_t nc = (size_t)c->p.nx * c->p.ny * c->p.nz;
+    if ((size_t)comps * nc * sizeof(double) > kScratchBytes)
+        return fail(PULBM_EINVAL, "case of %zu nodes exceeds the allocation-free read-back (at most %zu nodes in %dD)",
+                    nc, kScratchBytes / (sizeof(double) * comps), dim);
+    int cur = 0;
+    HIPC(hipGetDevice(&cur));
+    if (cur != c->device) HIPC(hipSetDevice(c->device));
+    int rc = PULBM_OK;
+    {
+        std::lock_guard<std::mutex> hold(g_scratch[c->device < kMaxDevices && c->device >= 0 ? c->device : 0].lock);
+        void* sp = nullptr;
+        rc = scratch_ptr(c->device, &sp);
+        if (!rc) rc = read_pass(c);
+        if (!rc) {
+            double* out = (double*)sp;
+            const void* fphi = c->h.phi[c->step & 1];
+            const void* fP = c->h.P[(c->step + 1) & 1];
+            const void* fU = c->h.U[c->step & 1];
+            const int64_t total = (int64_t)nc * comps;
+            const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
+            if (c->p.store == PULBM_STORE_FP64)
+                hipLaunchKernelGGL(k_pack_fields<double>, dim3(blocks), dim3(256), 0, c->stream, (const double*)fphi,
+                                   (const double*)fP, (const double*)fU, c->h.N, c->p.nx, c->h.sx, (int64_t)nc,
+                                   comps, out);
+            else
+                hipLaunchKernelGGL(k_pack_fields<float>, dim3(blocks), dim3(256), 0, c->stream, (const float*)fphi,
+                                   (const float*)fP, (const float*)fU, c->h.N, c->p.nx, c->h.sx, (int64_t)nc,
+                                   comps, out);
+            hipError_t e = hipGetLastError();
+            if (e == hipSuccess) e = hipMemcpyAsync(phi, out, nc * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+            if (e == hipSuccess) e = hipMemcpyAsync(P, out + nc, nc * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(u, out + 2 * nc, (size_t)dim * nc * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            if (e != hipSuccess) rc = fail(PULBM_EDEVICE, "allocation-free read-back failed: %s", hipGetErrorString(e));
+        }
+    }
+    if (cur != c->device) (void)hipSetDevice(cur);
+    return rc;
 }
 
 extern "C" int pulbm_diagnostics(pulbm_case* c, pulbm_diag* d)

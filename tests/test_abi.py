@@ -47,7 +47,7 @@ def lib():
 
 def test_header_matches_exports_and_binding(lib):
     decl = _declared()
-    assert len(decl) == 22
+    assert len(decl) == 23
     assert decl == _exported()
     assert decl == set(B.EXPORTS)
     for name in decl:
