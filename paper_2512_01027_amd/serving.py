@@ -78,7 +78,8 @@ def _summary(reqs, makespan):
 
 
 def run_batched(reqs, hbm_budget: int, store: str = "fp16", k: int = 50, max_slots: int = 64,
-                fill_nodes: int = 12 << 20, admit_per_round: int = 4, policy: str = "fifo"):
+                fill_nodes: int = 12 << 20, admit_per_round: int = 4, policy: str = "fifo",
+                big_nodes: int = 3 << 19, progress=None):
     """Continuous batching.  Returns the summary; sets each request's done.
 
     Waiting requests are admitted in arrival order ("fifo") or least work
@@ -86,8 +87,20 @@ def run_batched(reqs, hbm_budget: int, store: str = "fp16", k: int = 50, max_slo
     the first ones while later ones are set up, and only while the resident
     cases hold fewer than fill_nodes nodes (enough to fill the GPU: more would
     only share it among more cases and lengthen every latency).
+
+    "big_fifo": a request of at least big_nodes nodes (one that fills the GPU
+    on its own) is admitted only when no other such case is resident, in
+    arrival order, so large cases run one after another at nearly the full
+    rate, as one at a time would run them; smaller requests are admitted in
+    arrival order alongside, while the resident small cases hold fewer than
+    fill_nodes nodes, and may overtake a large request that waits.  A small
+    request then never queues behind a large one, and a large one never
+    shares the GPU with another large one.
+
+    progress(finished, total, elapsed), when given, is called after every
+    completion.
     """
-    if policy not in ("fifo", "sjf"):
+    if policy not in ("fifo", "sjf", "big_fifo"):
         raise ValueError(f"unknown admission policy {policy!r}")
     bt = B.Batch(hbm_budget, store=store, max_slots=max_slots)
     pending = sorted(reqs, key=lambda r: r.arrival)
@@ -105,7 +118,30 @@ def run_batched(reqs, hbm_budget: int, store: str = "fp16", k: int = 50, max_slo
         if policy == "sjf":
             waiting.sort(key=lambda r: (r.work, r.arrival))
         admitted = 0
-        while waiting and admitted < admit_per_round:
+        if policy == "big_fifo":
+            big_resident = any(r.nodes >= big_nodes for r in resident.values())
+            small_held = sum(r.nodes for r in resident.values() if r.nodes < big_nodes)
+            i_w = 0
+            while i_w < len(waiting) and admitted < admit_per_round:
+                r = waiting[i_w]
+                big = r.nodes >= big_nodes
+                if big and big_resident:
+                    i_w += 1  # waits; later small requests may pass it
+                    continue
+                if not big and small_held and small_held + r.nodes > fill_nodes:
+                    i_w += 1
+                    continue
+                slot = bt.admit(r.cfg, *r.fields, r.steps)
+                if slot is None:
+                    break
+                resident[slot] = r
+                waiting.pop(i_w)
+                admitted += 1
+                if big:
+                    big_resident = True
+                else:
+                    small_held += r.nodes
+        while policy != "big_fifo" and waiting and admitted < admit_per_round:
             held = sum(r.nodes for r in resident.values())
             if resident and held + waiting[0].nodes > fill_nodes:
                 break
@@ -127,6 +163,8 @@ def run_batched(reqs, hbm_budget: int, store: str = "fp16", k: int = 50, max_slo
             bt.take(s)
             r.done = time.perf_counter() - t0
             finished += 1
+            if progress is not None:
+                progress(finished, len(reqs), r.done)
     makespan = max(r.done for r in reqs) - min(r.arrival for r in reqs)
     bt.close()
     out = _summary(reqs, makespan)
@@ -134,10 +172,10 @@ def run_batched(reqs, hbm_budget: int, store: str = "fp16", k: int = 50, max_slo
     return out
 
 
-def run_sequential(reqs):
+def run_sequential(reqs, progress=None):
     """One case at a time, first come first served, single-case API."""
     t0 = time.perf_counter()
-    for r in sorted(reqs, key=lambda r: r.arrival):
+    for k, r in enumerate(sorted(reqs, key=lambda r: r.arrival)):
         now = time.perf_counter() - t0
         if now < r.arrival:
             time.sleep(r.arrival - now)
@@ -147,6 +185,8 @@ def run_sequential(reqs):
         c.read_fields()
         c.close()
         r.done = time.perf_counter() - t0
+        if progress is not None:
+            progress(k + 1, len(reqs), r.done)
     makespan = max(r.done for r in reqs) - min(r.arrival for r in reqs)
     return _summary(reqs, makespan)
 
@@ -155,3 +195,86 @@ def compare(batched: dict, sequential: dict) -> dict:
     return {"batched": batched, "sequential": sequential,
             "throughput_ratio": round(batched["MLUPS"] / sequential["MLUPS"], 3),
             "p99_ratio": round(batched["latency_p99_s"] / sequential["latency_p99_s"], 3)}
+
+
+def _records(reqs):
+    return [{"rid": r.rid, "nodes": r.nodes, "steps": r.steps, "kind": r.kind, "dim": r.cfg["dim"],
+             "arrival_s": round(r.arrival, 4), "done_s": round(r.done, 4),
+             "latency_s": round(r.done - r.arrival, 4)} for r in reqs]
+
+
+def main(argv=None):
+    """The serving stream at its stated size, one mode per run:
+
+        python -m paper_2512_01027_amd.serving batched    --cases 500 --rate auto --out F
+        python -m paper_2512_01027_amd.serving sequential --cases 500 --rate R    --out F
+
+    The request stream (seed 3) has full step counts (1000..10000).  --rate
+    auto calibrates the capacity on a saturated burst of the first --calib
+    requests (batched, big_fifo) and sets the Poisson rate to 0.8 x that
+    capacity / the stream's mean work; give the printed rate to the other
+    mode's run.  Each completion is printed as it happens; --out receives one
+    JSON line per request and a summary line."""
+    import argparse
+    import json
+    import sys
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("mode", choices=("batched", "sequential"))
+    ap.add_argument("--cases", type=int, default=500)
+    ap.add_argument("--step-scale", type=float, default=1.0)
+    ap.add_argument("--rate", default="auto")
+    ap.add_argument("--calib", type=int, default=40)
+    ap.add_argument("--policy", default="big_fifo")
+    ap.add_argument("--fill-nodes", type=int, default=4 << 20)
+    ap.add_argument("--k", type=int, default=50)
+    ap.add_argument("--budget-frac", type=float, default=0.8)
+    ap.add_argument("--out", required=True)
+    a = ap.parse_args(argv)
+    t0 = time.perf_counter()
+    reqs = make_stream(a.cases, "fp16", a.step_scale)
+    print(f"stream of {len(reqs)} requests built in {time.perf_counter() - t0:.0f} s", flush=True)
+    mean_work = sum(r.work for r in reqs) / len(reqs)
+    import torch
+
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(a.budget_frac * free)
+    out = {"mode": a.mode, "cases": len(reqs), "step_scale": a.step_scale, "mean_work": mean_work,
+           "budget_GiB": round(budget / 2 ** 30, 1)}
+    if a.rate == "auto":
+        calib = reqs[: a.calib]
+        set_arrivals(calib, None)
+        cap = run_batched(calib, budget, k=a.k, policy=a.policy, fill_nodes=a.fill_nodes)
+        rate = 0.8 * cap["MLUPS"] * 1e6 / mean_work
+        out["calibration"] = cap
+        print(f"calibration: {cap['MLUPS']} MLUPS on {len(calib)} requests -> rate {rate:.6f}/s", flush=True)
+    else:
+        rate = float(a.rate)
+    out["rate_per_s"] = rate
+    set_arrivals(reqs, rate)
+
+    last = [time.perf_counter()]
+
+    def progress(k, n, t):
+        if k % 10 == 0 or k == n or time.perf_counter() - last[0] > 30:
+            last[0] = time.perf_counter()
+            print(f"{a.mode}: {k}/{n} done at {t:.1f} s", flush=True)
+
+    if a.mode == "batched":
+        res = run_batched(reqs, budget, k=a.k, policy=a.policy, fill_nodes=a.fill_nodes, progress=progress)
+    else:
+        res = run_sequential(reqs, progress=progress)
+    out["summary"] = res
+    with open(a.out, "w") as f:
+        for rec in _records(reqs):
+            f.write(json.dumps(rec) + "\n")
+        f.write(json.dumps(out) + "\n")
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    import sys
+
+    sys.exit(main())
+

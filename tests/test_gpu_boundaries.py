@@ -49,6 +49,12 @@ CASES = {
                             block=((8, 5, 0), (13, 11, 5)), R=5.0, center=(26.4, 8.3, 7.1)),
     "2d_dam_geometry": dict(dim=2, nx=70, ny=33, wall=(1, 2, 0), gravity=(0.0, -1e-5, 0.0), p_top=0.01,
                             block=((20, 0, 0), (27, 6, 1)), R=7.0, center=(45.3, 12.6, 0.0)),
+    # full 64-node rows: tiles at the walls and the open top away from the
+    # block read their halo rows as vectors; those next to it cell by cell
+    "3d_dam_full_rows": dict(dim=3, nx=128, ny=10, nz=12, wall=(1, 1, 2), gravity=(0.0, 0.0, -1e-5), p_top=0.02,
+                             block=((10, 3, 0), (16, 7, 4)), R=4.0, center=(90.3, 5.4, 6.2)),
+    "2d_dam_full_rows": dict(dim=2, nx=128, ny=33, wall=(1, 2, 0), gravity=(0.0, -1e-5, 0.0), p_top=0.01,
+                             block=((20, 0, 0), (27, 6, 1)), R=7.0, center=(95.3, 12.6, 0.0)),
 }
 
 

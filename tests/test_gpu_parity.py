@@ -58,6 +58,10 @@ CASES = {
     # the ragged last one cell by cell
     "3d_periodic_wide": dict(dim=3, nx=70, ny=9, nz=7),
     "3d_walls_y_wide": dict(dim=3, nx=130, ny=8, nz=6, wall=(0, 1, 0), gravity=(0.0, -1e-5, 0.0)),
+    # full 64-node rows in tiles at walls on every axis: their halo rows are
+    # read as vectors, ghost rows and end cells mirrored
+    "3d_all_walls_full_rows": dict(dim=3, nx=128, ny=6, nz=5, wall=(1, 1, 1), gravity=(1e-6, 2e-6, -1e-5)),
+    "2d_walls_full_rows": dict(dim=2, nx=128, ny=13, wall=(1, 1, 0), gravity=(2e-6, -1e-5, 0.0)),
 }
 
 
@@ -169,7 +173,7 @@ def test_static_droplet_2d_config_full_run():
 
 
 @pytest.mark.parametrize("store,tol", [("fp32", 2e-5)])
-@pytest.mark.parametrize("case", ["3d_walls_z_gravity", "2d_walls_gravity", "3d_walls_y_wide"])
+@pytest.mark.parametrize("case", ["3d_walls_z_gravity", "2d_walls_gravity", "3d_walls_y_wide", "3d_all_walls_full_rows"])
 def test_fp32_matches_oracle(store, tol, case):
     kw = dict(CASES[case])
     dim, nx, ny = kw.pop("dim"), kw.pop("nx"), kw.pop("ny")

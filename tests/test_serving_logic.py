@@ -87,6 +87,24 @@ def test_least_work_first_admits_smallest_work_first(fake):
     assert order == [3, 1, 4, 2, 0]
 
 
+def test_big_fifo_runs_large_cases_one_at_a_time(fake):
+    """Large requests (>= big_nodes) one at a time in arrival order; small
+    ones alongside within the fill limit, passing a large one that waits."""
+    reqs = _reqs([(500, 100), (600, 100), (10, 50), (20, 50), (700, 100), (30, 400)])
+    SV.run_batched(reqs, hbm_budget=10 ** 9, k=50, fill_nodes=40, admit_per_round=8, policy="big_fifo",
+                   big_nodes=400)
+    log = [e for e in fake.log if e[0] == "admit"]
+    order = [e[1] for e in log]
+    # the first large one, then the small ones pass the waiting second large one
+    assert order[:3] == [0, 2, 3]
+    assert order.index(1) < order.index(4)
+    for e in log:
+        res = e[2]
+        assert sum(1 for n in res if n >= 400) <= 1
+        assert sum(n for n in res if n < 400) <= 40 or sum(1 for n in res if n < 400) == 1
+    assert all(not math.isnan(r.done) for r in reqs)
+
+
 def test_fill_limit_and_refusals(fake):
     reqs = _reqs([(60, 100)] * 6 + [(250, 50)])
     orig_init = FakeBatch.__init__
