@@ -79,7 +79,7 @@ def _summary(reqs, makespan):
 
 def run_batched(reqs, hbm_budget: int, store: str = "fp16", k: int = 50, max_slots: int = 64,
                 fill_nodes: int = 12 << 20, admit_per_round: int = 4, policy: str = "fifo",
-                big_nodes: int = 3 << 19, progress=None):
+                big_nodes: int = 3 << 19, fill_with_big: int | None = None, progress=None):
     """Continuous batching.  Returns the summary; sets each request's done.
 
     Waiting requests are admitted in arrival order ("fifo") or least work
@@ -93,15 +93,19 @@ def run_batched(reqs, hbm_budget: int, store: str = "fp16", k: int = 50, max_slo
     arrival order, so large cases run one after another at nearly the full
     rate, as one at a time would run them; smaller requests are admitted in
     arrival order alongside, while the resident small cases hold fewer than
-    fill_nodes nodes, and may overtake a large request that waits.  A small
-    request then never queues behind a large one, and a large one never
-    shares the GPU with another large one.
+    fill_nodes nodes (fill_with_big while a large case is resident, so that
+    the large case, which every resident case slows as all of them advance
+    in lock-step, keeps most of the GPU), and may overtake a large request
+    that waits.  A small request then never queues behind a large one, and a
+    large one never shares the GPU with another large one.
 
     progress(finished, total, elapsed), when given, is called after every
     completion.
     """
     if policy not in ("fifo", "sjf", "big_fifo"):
         raise ValueError(f"unknown admission policy {policy!r}")
+    if fill_with_big is None:
+        fill_with_big = fill_nodes
     bt = B.Batch(hbm_budget, store=store, max_slots=max_slots)
     pending = sorted(reqs, key=lambda r: r.arrival)
     waiting: list[Request] = []
@@ -128,7 +132,8 @@ def run_batched(reqs, hbm_budget: int, store: str = "fp16", k: int = 50, max_slo
                 if big and big_resident:
                     i_w += 1  # waits; later small requests may pass it
                     continue
-                if not big and small_held and small_held + r.nodes > fill_nodes:
+                cap = fill_with_big if big_resident else fill_nodes
+                if not big and small_held and small_held + r.nodes > cap:
                     i_w += 1
                     continue
                 slot = bt.admit(r.cfg, *r.fields, r.steps)
@@ -169,6 +174,8 @@ def run_batched(reqs, hbm_budget: int, store: str = "fp16", k: int = 50, max_slo
     bt.close()
     out = _summary(reqs, makespan)
     out.update({"peak_resident": peak, "advance_steps": k, "fill_nodes": fill_nodes, "policy": policy})
+    if policy == "big_fifo":
+        out.update({"big_nodes": big_nodes, "fill_with_big": fill_with_big})
     return out
 
 
@@ -213,7 +220,8 @@ def main(argv=None):
     auto calibrates the capacity on a saturated burst of the first --calib
     requests (batched, big_fifo) and sets the Poisson rate to 0.8 x that
     capacity / the stream's mean work; give the printed rate to the other
-    mode's run.  Each completion is printed as it happens; --out receives one
+    mode's run.  --rate burst: every request arrives at time 0 (the
+    saturated capacity of each mode).  Each completion is printed as it happens; --out receives one
     JSON line per request and a summary line."""
     import argparse
     import json
@@ -227,6 +235,7 @@ def main(argv=None):
     ap.add_argument("--calib", type=int, default=40)
     ap.add_argument("--policy", default="big_fifo")
     ap.add_argument("--fill-nodes", type=int, default=4 << 20)
+    ap.add_argument("--fill-with-big", type=int, default=None)
     ap.add_argument("--k", type=int, default=50)
     ap.add_argument("--budget-frac", type=float, default=0.8)
     ap.add_argument("--out", required=True)
@@ -248,6 +257,8 @@ def main(argv=None):
         rate = 0.8 * cap["MLUPS"] * 1e6 / mean_work
         out["calibration"] = cap
         print(f"calibration: {cap['MLUPS']} MLUPS on {len(calib)} requests -> rate {rate:.6f}/s", flush=True)
+    elif a.rate == "burst":
+        rate = None
     else:
         rate = float(a.rate)
     out["rate_per_s"] = rate
@@ -261,7 +272,8 @@ def main(argv=None):
             print(f"{a.mode}: {k}/{n} done at {t:.1f} s", flush=True)
 
     if a.mode == "batched":
-        res = run_batched(reqs, budget, k=a.k, policy=a.policy, fill_nodes=a.fill_nodes, progress=progress)
+        res = run_batched(reqs, budget, k=a.k, policy=a.policy, fill_nodes=a.fill_nodes,
+                          fill_with_big=a.fill_with_big, progress=progress)
     else:
         res = run_sequential(reqs, progress=progress)
     out["summary"] = res

@@ -199,3 +199,40 @@ def test_batch_fp16_within_storage_tolerance():
         print(nm, e, flush=True)
         assert ok, (nm, e, bound)
 
+
+@pytest.mark.skip(reason="the persistent cooperative kernel is taken out of the library: it matched the graph "
+                         "advances bitwise on this mix, but its grid barrier timed out on a 64-case stream of "
+                         "cases up to 64^3 nodes, and the cause has not been shown")
+@pytest.mark.parametrize("store", ["fp16", "fp32", "fp64"])
+def test_persistent_advances_equal_graph_advances(store):
+    """The persistent cooperative kernel runs the cases of a mixed batch
+    (2D and 3D, D3Q27 and D3Q19, walls, block and open top, BGK) bitwise as
+    the graph of per-step launches does, including a case admitted part-way
+    and advances of different lengths."""
+    cases = _cases(store)
+    got = {}
+    for persistent in (False, True):
+        bt = B.Batch(1 << 30, store=store, max_slots=8)
+        if persistent:
+            bt.set_persistent(True)
+        slots = {}
+        for k in (0, 1, 2, 4, 5, 6):
+            cfg, f, n = cases[k]
+            slots[bt.admit(cfg, *f, n)] = k
+        res = {}
+        adv = 0
+        while len(res) < len(cases):
+            if adv == 16:
+                cfg, f, n = cases[3]
+                slots[bt.admit(cfg, *f, n)] = 3
+            kk = 8 if adv < 24 else 5
+            bt.advance(kk)
+            adv += kk
+            for s in bt.poll():
+                res[slots[s]] = bt.take(s)
+            assert adv < 200
+        bt.close()
+        got[persistent] = res
+    for k in range(len(cases)):
+        assert _same(got[True][k], got[False][k]), f"case {k} differs between persistent and graph advances"
+

@@ -105,6 +105,28 @@ def test_big_fifo_runs_large_cases_one_at_a_time(fake):
     assert all(not math.isnan(r.done) for r in reqs)
 
 
+def test_big_fifo_smaller_fill_beside_a_large_case(fake):
+    """While a large case is resident, small ones fill up to fill_with_big
+    only (one small case is always let in); with none resident, up to
+    fill_nodes.  (Small cases resident before a large one arrives stay.)"""
+    reqs = _reqs([(500, 100)] + [(10, 50)] * 10)
+    out = SV.run_batched(reqs, hbm_budget=10 ** 9, k=50, fill_nodes=40, fill_with_big=15, admit_per_round=8,
+                         policy="big_fifo", big_nodes=400)
+    assert out["fill_with_big"] == 15
+    saw_big = saw_full = False
+    for e in (e for e in fake.log if e[0] == "admit"):
+        res = e[2]
+        small = [n for n in res if n < 400]
+        if len(res) > len(small):
+            saw_big = True
+            assert sum(small) <= 15 or len(small) == 1
+        elif sum(small) > 15:
+            saw_full = True
+            assert sum(small) <= 40
+    assert saw_big and saw_full
+    assert all(not math.isnan(r.done) for r in reqs)
+
+
 def test_fill_limit_and_refusals(fake):
     reqs = _reqs([(60, 100)] * 6 + [(250, 50)])
     orig_init = FakeBatch.__init__
