@@ -81,7 +81,14 @@ struct CaseDev {
     int32_t fuse_u; // 1: the collide kernel rebuilds u itself and a step skips k_velocity
                     // (no wall, open end or block, 4- or 8-byte storage, every axis >= 3,
                     // D2Q9 or D3Q19 hydro)
-    int32_t pad1;
+    // The tile order's divisors -- ntx, tband ntz, tband and the last band's
+    // rows -- as multipliers M = floor(2^40 / d) + 1 split into high and low
+    // words, so that a block takes its tile apart with scalar multiplies:
+    // n / d = (n Mh + mulhi(n, Ml)) >> 8, exact while n d < 2^40 (fastdiv
+    // = 1, checked for every divisor against its largest dividend when the
+    // case is created; otherwise the kernels divide).
+    int32_t fastdiv;
+    uint32_t dvh[4], dvl[4];
 };
 
 using CDesc = const PULBM_CST CaseDev;
@@ -104,6 +111,14 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblocks)
 {
     const int per = nblocks >> 3;
     return (bid & 7) * per + (bid >> 3);
+}
+
+// n / d for the multiplier (mh, ml) of d (CaseDev::dvh, dvl): the high word
+// of n times the 40-bit multiplier, shifted down by 8.  n mh stays below 2^32
+// for n < 2^23 (mh <= 256).
+__device__ __forceinline__ uint32_t udiv_m(uint32_t n, uint32_t mh, uint32_t ml)
+{
+    return (n * mh + __umulhi(n, ml)) >> 8;
 }
 
 __device__ __forceinline__ int find_case(const PULBM_CST int* tstart, int ncases, int tile)
@@ -152,13 +167,27 @@ __device__ __forceinline__ TileCtx tile_ctx(CaseTab cases, const int* hdr_, int 
     // (a band's width of tiles apart), while each plane is still read in runs
     // of whole rows.
     int lt = tile - tstart[ci];
-    const int tx = lt % cs.ntx;
-    lt /= cs.ntx;
-    const int yb = lt / (cs.tband * cs.ntz);
-    const int rem = lt - yb * cs.tband * cs.ntz;
-    const int by = min(cs.tband, cs.nty - yb * cs.tband);
-    const int tz = rem / by;
-    const int ty = yb * cs.tband + rem % by;
+    int tx, ty, tz;
+    if (cs.fastdiv) {
+        const uint32_t l = (uint32_t)lt;
+        const uint32_t r = udiv_m(l, cs.dvh[0], cs.dvl[0]);
+        tx = (int)(l - r * (uint32_t)cs.ntx);
+        const uint32_t yb = udiv_m(r, cs.dvh[1], cs.dvl[1]);
+        const uint32_t rem = r - yb * (uint32_t)(cs.tband * cs.ntz);
+        const int rows = cs.nty - (int)yb * cs.tband;  // rows of this band: tband, or fewer in the last
+        const int k = rows < cs.tband ? 3 : 2;
+        const uint32_t tq = udiv_m(rem, cs.dvh[k], cs.dvl[k]);
+        tz = (int)tq;
+        ty = (int)yb * cs.tband + (int)(rem - tq * (uint32_t)min(cs.tband, rows));
+    } else {
+        tx = lt % cs.ntx;
+        lt /= cs.ntx;
+        const int yb = lt / (cs.tband * cs.ntz);
+        const int rem = lt - yb * cs.tband * cs.ntz;
+        const int by = min(cs.tband, cs.nty - yb * cs.tband);
+        tz = rem / by;
+        ty = yb * cs.tband + rem % by;
+    }
     t.ox = tx * Mo::TX;
     t.oy = ty * Mo::TY;
     t.oz = tz * Mo::TZ;

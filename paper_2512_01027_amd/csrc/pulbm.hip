@@ -152,6 +152,25 @@ int validate(const pulbm_params* p)
     return PULBM_OK;
 }
 
+// Multipliers of the tile order's divisors (CaseDev::dvh, dvl): M =
+// floor(2^40 / d) + 1 gives floor(n M / 2^40) = n / d for n d < 2^40, since
+// M d - 2^40 lies in [1, d].  fastdiv is set when that holds for every
+// divisor and its largest dividend, and the tile count is below 2^23.
+void tile_divisors(CaseDev& h, int64_t ntiles)
+{
+    const int64_t nb = (h.nty + h.tband - 1) / h.tband;
+    const int64_t d[4] = {h.ntx, (int64_t)h.tband * h.ntz, h.tband, h.nty - (nb - 1) * h.tband};
+    const int64_t nmax[4] = {ntiles, ntiles / h.ntx + 1, (int64_t)h.tband * h.ntz, (int64_t)h.tband * h.ntz};
+    bool ok = ntiles < (int64_t(1) << 23);
+    for (int k = 0; k < 4; ++k) {
+        const uint64_t m = (uint64_t(1) << 40) / (uint64_t)d[k] + 1;
+        h.dvh[k] = (uint32_t)(m >> 32);
+        h.dvl[k] = (uint32_t)m;
+        ok = ok && d[k] >= 1 && (uint64_t)nmax[k] * (uint64_t)d[k] < (uint64_t(1) << 40);
+    }
+    h.fastdiv = ok ? 1 : 0;
+}
+
 template <int LS> void tiles_of(const pulbm_params& p, int* ntx, int* nty, int* ntz)
 {
     using Mo = Model<LS>;
@@ -363,6 +382,7 @@ extern "C" int pulbm_create(const pulbm_params* p, void* dev_arena, size_t arena
     // y bands of about 64 tiles per z layer: z neighbours then run within
     // what one XCD holds at once (measured: 128^3 +1%, 256^3 +6%)
     h.tband = std::max(4, std::min(32, 64 / h.ntx));
+    tile_divisors(h, c->ntiles);
     h.delta_theta = p->delta_theta;
     h.sx = row_pitch(p->nx);
     h.N = (int64_t)h.sx * p->ny * p->nz;
