@@ -152,6 +152,16 @@ int pulbm_restore(pulbm_case* c, const void* host_buf, size_t bytes);
 /* Wait for all queued work of the case. */
 int pulbm_sync(pulbm_case* c);
 int64_t pulbm_steps_done(const pulbm_case* c);
+
+/* Race check of the in-place AA pattern and the tile-parallel kernels:
+ * order 1 makes every later launch of the case take its tiles in the
+ * reverse of the usual order (the workgroup that would take the first tile
+ * takes the last), so each tile runs on another workgroup, XCD and time.
+ * Within a step no workgroup may read what another one writes in the same
+ * launch, so results are bitwise those of order 0 (the default), which
+ * restores the usual order.  Queued on the case's stream; PULBM_EINVAL for
+ * a NULL case or an order other than 0 or 1. */
+int pulbm_set_tile_order(pulbm_case* c, int32_t order);
 void pulbm_destroy(pulbm_case* c);
 
 /* Message of the last failed call on this thread ("" if none). */

@@ -25,7 +25,7 @@ EXPORTS = [
     "pulbm_restore", "pulbm_sync", "pulbm_steps_done", "pulbm_destroy", "pulbm_last_error",
     "pulbm_batch_create", "pulbm_batch_admit", "pulbm_batch_advance", "pulbm_batch_poll",
     "pulbm_batch_take", "pulbm_batch_usage", "pulbm_batch_destroy", "pulbm_stream_copy",
-    "pulbm_read_fields_noalloc",
+    "pulbm_read_fields_noalloc", "pulbm_set_tile_order",
 ]
 
 
@@ -91,6 +91,7 @@ def load():
         "pulbm_restore": [vp, vp, sz],
         "pulbm_sync": [vp],
         "pulbm_steps_done": [vp],
+        "pulbm_set_tile_order": [vp, i32],
         "pulbm_destroy": [vp],
         "pulbm_last_error": [],
         "pulbm_batch_create": [sz, i32, i32, vp, C.POINTER(vp)],
@@ -226,6 +227,10 @@ class Case:
     @property
     def steps_done(self) -> int:
         return int(self.lib.pulbm_steps_done(self._h))
+
+    def set_tile_order(self, order: int):
+        """0: the usual tile order; 1: reversed (a race check, see pulbm.h)."""
+        _check(self.lib.pulbm_set_tile_order(self._h, int(order)))
 
     def read_fields(self):
         phi = np.empty(self.N)

@@ -89,6 +89,8 @@ struct CaseDev {
     // case is created; otherwise the kernels divide).
     int32_t fastdiv;
     uint32_t dvh[4], dvl[4];
+    int32_t tile_rev;  // 1: the case's tiles are taken in reverse order (a race check, pulbm_set_tile_order)
+    int32_t pad1;
 };
 
 using CDesc = const PULBM_CST CaseDev;
@@ -167,6 +169,7 @@ __device__ __forceinline__ TileCtx tile_ctx(CaseTab cases, const int* hdr_, int 
     // (a band's width of tiles apart), while each plane is still read in runs
     // of whole rows.
     int lt = tile - tstart[ci];
+    if (cs.tile_rev) lt = tstart[ci + 1] - tstart[ci] - 1 - lt;
     int tx, ty, tz;
     if (cs.fastdiv) {
         const uint32_t l = (uint32_t)lt;
@@ -1266,7 +1269,14 @@ __device__ __forceinline__ void tile_gradients(const CT* sPhi, const CT* sRho, c
 // incoming h (parked in LDS until the direction loop) and M2,
 // together with the halo loads of phi and u, so that their latencies overlap;
 // then it takes the gradients from LDS and collides one direction at a time.
-template <int LS, class S, bool WALL, bool BGK, class R>
+// The tile's step read again from the descriptor (a volatile load, so the
+// compiler cannot take it for the value a branch already tested).
+__device__ __forceinline__ int64_t step_parity(CDesc& cs, const TileCtx& t)
+{
+    return *(const volatile PULBM_CST int64_t*)&cs.step + (t.step - cs.step);
+}
+
+template <int LS, class S, bool WALL, bool BGK, class R, int PAR>
 __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typename Codec<S>::CT* sPhi,
                                              typename Codec<S>::CT* sRho,
                                              typename Codec<S>::CT (*sU)[R::N], S (*sH)[256],
@@ -1287,7 +1297,12 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
     const bool inside = x < cs.nx && y < cs.ny && z < cs.nz && !(WALL && in_block(cs, x, y, z));
     const uint32_t n = inside ? (uint32_t)x + (uint32_t)cs.sx * ((uint32_t)y + (uint32_t)cs.ny * (uint32_t)z) : 0u;
     const uint32_t nb = n * (uint32_t)sizeof(S), na = n * (uint32_t)sizeof(CT);
-    const bool odd = t.step & 1;
+    // the step's parity, which decides the slots the AA pattern reads and
+    // writes: PAR 0, even, fixed at compile time; PAR 1, odd, but read again
+    // at run time (step_parity), so that each load and store decides its slot
+    // as it runs: a copy with the odd slots fixed needs more registers than
+    // the 3-waves budget and spills
+    const bool odd = PAR == 0 ? false : (bool)(step_parity(cs, t) & 1);
     const Nav nv = make_nav(cs, inside ? x : 0, inside ? y : 0, inside ? z : 0, (int)sizeof(S));
     const Slots<S> hs = slots<S>(cs.h, cs.N), gs = slots<S>(cs.g, cs.N);
     // own-node loads first
@@ -1511,7 +1526,14 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
 // costs a few dwords of spill and hides enough more memory latency to run
 // 10% (FP32) to 18% (FP16) faster; 128 (4 waves) spills too much.
 #define PULBM_COLLIDE_ATTR __attribute__((amdgpu_waves_per_eu(3, 3)))
-template <int LS, class S, bool BGK>
+// One kernel per step parity: PAR 0 takes the tiles of cases at an even
+// step, with every load and store on its fixed slot (no branch: the FP16
+// collide's even steps run 17% faster than with the parity read at run
+// time); PAR 1 takes the tiles of cases at an odd step.  A single case
+// launches the kernel of its step's parity, a serving batch (whose cases may
+// differ in parity) both, each skipping the other's tiles, so a case runs the
+// same code alone and in a batch, bitwise.
+template <int LS, class S, bool BGK, int PAR>
 __global__ __launch_bounds__(256) PULBM_COLLIDE_ATTR void k_collide(CaseTab cases, const int* hdr, int step_off)
 {
     constexpr int DIMV = Model<LS>::DIM;
@@ -1524,10 +1546,10 @@ __global__ __launch_bounds__(256) PULBM_COLLIDE_ATTR void k_collide(CaseTab case
     // the new P two nodes deep, for cases whose collide rebuilds u (4- and 8-byte storage)
     __shared__ CT sP2[sizeof(S) >= 4 ? Halo2<Mo, DIMV>::R::N : 1];
     const TileCtx t = tile_ctx<Mo>(cases, hdr, step_off);
-    if (!t.active) return;
+    if (!t.active || (int)(t.step & 1) != PAR) return;
     CDesc& cs = *t.cs;
-    if (tile_at_wall<Mo>(cs, t.ox, t.oy, t.oz)) collide_tile<LS, S, true, BGK, R>(cs, t, sPhi, sRho, sU, sH, sP2);
-    else collide_tile<LS, S, false, BGK, R>(cs, t, sPhi, sRho, sU, sH, sP2);
+    if (tile_at_wall<Mo>(cs, t.ox, t.oy, t.oz)) collide_tile<LS, S, true, BGK, R, PAR>(cs, t, sPhi, sRho, sU, sH, sP2);
+    else collide_tile<LS, S, false, BGK, R, PAR>(cs, t, sPhi, sRho, sU, sH, sP2);
 }
 
 // --- initial state: equilibria of (phi0, P0, u0) in the even AA layout,

@@ -208,7 +208,8 @@ struct pulbm_case {
 namespace {
 
 template <int LS, class S>
-void launch_step(hipStream_t st, CaseDev* const* tab, const int* hdr, int blocks, int off, int which, bool bgk)
+void launch_step(hipStream_t st, CaseDev* const* tab, const int* hdr, int blocks, int off, int which, bool bgk,
+                 int parity)
 {
     using CT = typename Codec<S>::CT;
     const dim3 grid(blocks), block(256);
@@ -216,31 +217,42 @@ void launch_step(hipStream_t st, CaseDev* const* tab, const int* hdr, int blocks
     if (which == 1) hipLaunchKernelGGL((k_pressure<LS, CT>), grid, block, 0, st, tab, hdr, off);
     if (which == 2) hipLaunchKernelGGL((k_velocity<LS, CT>), grid, block, 0, st, tab, hdr, off);
     if (which == 3) {
-        if (bgk) hipLaunchKernelGGL((k_collide<LS, S, true>), grid, block, 0, st, tab, hdr, off);
-        else hipLaunchKernelGGL((k_collide<LS, S, false>), grid, block, 0, st, tab, hdr, off);
+        // the collide kernel of each parity present (each skips the other's tiles)
+        if (parity != 1) {
+            if (bgk) hipLaunchKernelGGL((k_collide<LS, S, true, 0>), grid, block, 0, st, tab, hdr, off);
+            else hipLaunchKernelGGL((k_collide<LS, S, false, 0>), grid, block, 0, st, tab, hdr, off);
+        }
+        if (parity != 0) {
+            if (bgk) hipLaunchKernelGGL((k_collide<LS, S, true, 1>), grid, block, 0, st, tab, hdr, off);
+            else hipLaunchKernelGGL((k_collide<LS, S, false, 1>), grid, block, 0, st, tab, hdr, off);
+        }
     }
 }
 
 template <int LS>
 void launch_dim(int store, hipStream_t st, CaseDev* const* tab, const int* hdr, int blocks, int off, int which,
-                bool bgk)
+                bool bgk, int parity)
 {
     switch (store) {
-        case PULBM_STORE_FP64: launch_step<LS, double>(st, tab, hdr, blocks, off, which, bgk); break;
-        case PULBM_STORE_FP32: launch_step<LS, float>(st, tab, hdr, blocks, off, which, bgk); break;
-        case PULBM_STORE_FP16: launch_step<LS, _Float16>(st, tab, hdr, blocks, off, which, bgk); break;
-        default: launch_step<LS, uint16_t>(st, tab, hdr, blocks, off, which, bgk); break;
+        case PULBM_STORE_FP64: launch_step<LS, double>(st, tab, hdr, blocks, off, which, bgk, parity); break;
+        case PULBM_STORE_FP32: launch_step<LS, float>(st, tab, hdr, blocks, off, which, bgk, parity); break;
+        case PULBM_STORE_FP16: launch_step<LS, _Float16>(st, tab, hdr, blocks, off, which, bgk, parity); break;
+        default: launch_step<LS, uint16_t>(st, tab, hdr, blocks, off, which, bgk, parity); break;
     }
 }
 
 // which: 0 moments, 1 pressure, 2 velocity, 3 collide + stream.  blocks must
 // cover the table's tiles (rounded up to a multiple of 8); extra blocks exit.
+// parity: the step parity of every case of the table for this launch (its
+// device step counter plus off), 0 or 1, when the host knows it (a single
+// case); -1 when cases may differ (serving batches): then the collide
+// kernels of both parities are launched.
 void launch(int ls, int store, bool bgk, hipStream_t st, CaseDev* const* tab, const int* hdr, int blocks, int off,
-            int which)
+            int which, int parity = -1)
 {
-    if (ls == 2) launch_dim<2>(store, st, tab, hdr, blocks, off, which, bgk);
-    else if (ls == 4) launch_dim<4>(store, st, tab, hdr, blocks, off, which, bgk);
-    else launch_dim<3>(store, st, tab, hdr, blocks, off, which, bgk);
+    if (ls == 2) launch_dim<2>(store, st, tab, hdr, blocks, off, which, bgk, parity);
+    else if (ls == 4) launch_dim<4>(store, st, tab, hdr, blocks, off, which, bgk, parity);
+    else launch_dim<3>(store, st, tab, hdr, blocks, off, which, bgk, parity);
 }
 
 template <int LS, class S>
@@ -486,12 +498,13 @@ extern "C" int pulbm_init_fields(pulbm_case* c, const double* phi, const double*
 // count steps: kernels at step offsets 0 .. count-1, then the step counter.
 // (Replaying captured graphs instead was measured: 5% slower on a 128^3 case,
 // 3% faster on an 80k-node 2D case; direct launches are kept.)
-static void queue_direct(pulbm_case* c, int count)
+static void queue_direct(pulbm_case* c, int64_t first, int count)
 {
     for (int k = 0; k < count; ++k)
         for (int w = 0; w < kStepKernels; ++w)
             if (w != kVelocityKernel || !c->h.fuse_u)
-                launch(lattice_set(c->p.dim, c->p.q_hydro), c->p.store, c->p.collision == 1, c->stream, c->tab, c->hdr, grid_of(c->ntiles), k, w);
+                launch(lattice_set(c->p.dim, c->p.q_hydro), c->p.store, c->p.collision == 1, c->stream, c->tab,
+                       c->hdr, grid_of(c->ntiles), k, w, (int)((first + k) & 1));
     hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, c->stream, c->tab, c->hdr, count);
 }
 
@@ -500,7 +513,7 @@ static int queue_steps(pulbm_case* c, int64_t nsteps)
     int64_t s = 0;
     for (; s < nsteps;) {
         const int chunk = (int)std::min<int64_t>(nsteps - s, 1 << 20);
-        queue_direct(c, chunk);
+        queue_direct(c, c->step + s, chunk);
         HIPC(hipGetLastError());
         s += chunk;
     }
@@ -528,7 +541,8 @@ extern "C" int pulbm_step_timed(pulbm_case* c, int64_t nsteps, double* ms)
         (void)hipEventRecord(ev[0], c->stream);
         for (int w = 0; w < kStepKernels; ++w) {
             if (w != kVelocityKernel || !c->h.fuse_u)
-                launch(lattice_set(c->p.dim, c->p.q_hydro), c->p.store, c->p.collision == 1, c->stream, c->tab, c->hdr, grid_of(c->ntiles), 0, w);
+                launch(lattice_set(c->p.dim, c->p.q_hydro), c->p.store, c->p.collision == 1, c->stream, c->tab,
+                       c->hdr, grid_of(c->ntiles), 0, w, (int)(c->step & 1));
             (void)hipEventRecord(ev[w + 1], c->stream);
         }
         hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, c->stream, c->tab, c->hdr, 1);
@@ -803,6 +817,14 @@ extern "C" int pulbm_sync(pulbm_case* c)
 }
 
 extern "C" int64_t pulbm_steps_done(const pulbm_case* c) { return c ? c->step : -1; }
+
+extern "C" int pulbm_set_tile_order(pulbm_case* c, int32_t order)
+{
+    if (!c) return fail(PULBM_EINVAL, "case is NULL");
+    if (order != 0 && order != 1) return fail(PULBM_EINVAL, "order must be 0 or 1");
+    c->h.tile_rev = order;
+    return upload_desc(c);
+}
 
 // ============================================================= measurement
 

@@ -47,7 +47,7 @@ def lib():
 
 def test_header_matches_exports_and_binding(lib):
     decl = _declared()
-    assert len(decl) == 23
+    assert len(decl) == 24
     assert decl == _exported()
     assert decl == set(B.EXPORTS)
     for name in decl:
@@ -146,6 +146,7 @@ def test_null_handles(lib):
     assert lib.pulbm_required_bytes(None, None) == B.EINVAL
     assert lib.pulbm_step(None, 1) == B.EINVAL
     assert lib.pulbm_steps_done(None) == -1
+    assert lib.pulbm_set_tile_order(None, 1) == B.EINVAL
     lib.pulbm_destroy(None)
     lib.pulbm_batch_destroy(None)
     assert lib.pulbm_batch_create(0, 2, 4, None, None) == B.EINVAL

@@ -175,9 +175,19 @@ def test_static_droplet_2d_config_full_run():
 @pytest.mark.parametrize("store,tol", [("fp32", 2e-5)])
 @pytest.mark.parametrize("case", ["3d_walls_z_gravity", "2d_walls_gravity", "3d_walls_y_wide", "3d_all_walls_full_rows"])
 def test_fp32_matches_oracle(store, tol, case):
+    """FP32 storage element by element against the FP64 reference, without
+    delta theta: its sign switch s = L phi / (|L phi| + eps) (Sec. II) is
+    discontinuous where L phi is at FP32 rounding level, so a node where the
+    two arithmetics round L phi to opposite signs moves the FP32 result by
+    far more than its rounding (up to 2e-5 at 30 steps and 4e-4 at 60 on these
+    grids, against about 1e-6 without the switch); which nodes flip follows
+    the compiler's instruction order.  FP64 keeps delta theta at 1e-10, and
+    the FP32 / FP16 precision tests keep it, gated against the reference's
+    own spread."""
     kw = dict(CASES[case])
     dim, nx, ny = kw.pop("dim"), kw.pop("nx"), kw.pop("ny")
     nz = kw.pop("nz", 1)
+    kw["delta_theta"] = 0
     cfg = W.base_case(dim, nx, ny, nz, nu_heavy=0.05, nu_light=0.15, store=store, **kw)
     f = _fields(cfg)
     g = B.Case(cfg)
@@ -344,10 +354,13 @@ def test_bgk_collision_matches_oracle(case, store, tol):
 @pytest.mark.parametrize("case", ["3d_periodic_ragged", "3d_walls_z_gravity", "3d_all_walls", "3d_periodic_wide"])
 def test_d3q19_hydro_matches_oracle(case, collision, store, tol):
     """D3Q19 for the hydrodynamic populations as well as the phase field
-    (the lattice of the paper's 3D runs, Sec. II)."""
+    (the lattice of the paper's 3D runs, Sec. II).  FP32 runs without delta
+    theta, for the reason given in test_fp32_matches_oracle."""
     kw = dict(CASES[case])
     dim, nx, ny = kw.pop("dim"), kw.pop("nx"), kw.pop("ny")
     nz = kw.pop("nz", 1)
+    if store != "fp64":
+        kw["delta_theta"] = 0
     nu = (0.05, 0.15) if collision == "filter" else (0.1, 0.1)
     cfg = W.base_case(dim, nx, ny, nz, q_hydro=19, nu_heavy=nu[0], nu_light=nu[1], sigma=0.01,
                       store=store, collision=collision, **kw)
