@@ -61,9 +61,12 @@ _CT = {"fp64": "double", "fp32": "float", "fp16": "_Float16", "bf16": "unsigned 
 
 
 def kernel_names(ls, store):
+    """rocprofv3 names of a step's kernels; the collide kernel is one per step
+    parity (even, odd), and a step runs one of them."""
     s, a = _CT[store], ("double" if store == "fp64" else "float")
     return {"moments": f"pulbm::k_moments<{ls}, {s}>", "pressure": f"pulbm::k_pressure<{ls}, {a}>",
-            "velocity": f"pulbm::k_velocity<{ls}, {a}>", "collide": f"pulbm::k_collide<{ls}, {s}, false>"}
+            "velocity": f"pulbm::k_velocity<{ls}, {a}>",
+            "collide": (f"pulbm::k_collide<{ls}, {s}, false, 0>", f"pulbm::k_collide<{ls}, {s}, false, 1>")}
 
 
 def kernel_bytes(store_bytes, aux_bytes=4, pops=46, dim=3, q_phase=19):
@@ -164,12 +167,14 @@ def step_traffic(workload, ls, store, nodes):
     names = kernel_names(ls, store)
     per = {}
     for k, name in names.items():
-        r = rec["kernels"].get(name)
-        if r is None:
+        # a per-parity pair counts as the mean of its two launches
+        group = name if isinstance(name, tuple) else (name,)
+        rs = [rec["kernels"].get(nm) for nm in group]
+        if any(r is None for r in rs):
             if k == "velocity":
                 continue
             return None, None
-        per[k] = int(round(r["read_bytes"] + r["write_bytes"]))
+        per[k] = int(round(sum(r["read_bytes"] + r["write_bytes"] for r in rs) / len(rs)))
     return sum(per.values()), per
 
 

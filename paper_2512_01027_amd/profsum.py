@@ -33,8 +33,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ("csrc/kernels.hpp", "csrc/lattice.hpp", "csrc/codec.hpp", "csrc/pulbm.hip")
 
 # rocprofv3 leaves kernels templated on _Float16 in their mangled form:
-# _ZN5pulbm<len><name>ILi<lattice set>E<type>[Lb<0|1>E]E...
-_MANGLED = re.compile(r"_ZN5pulbm\d+(k_[a-z]+)ILi(\d)E(DF16_|[dft])(?:Lb([01])E)?E")
+# _ZN5pulbm<len><name>ILi<lattice set>E<type>[Lb<0|1>E[Li<parity>E]]E...
+_MANGLED = re.compile(r"_ZN5pulbm\d+(k_[a-z]+)ILi(\d)E(DF16_|[dft])(?:Lb([01])E(?:Li(\d)E)?)?E")
 _TYPES = {"DF16_": "_Float16", "d": "double", "f": "float", "t": "unsigned short"}
 
 
@@ -50,7 +50,8 @@ def short(name: str) -> str:
     m = _MANGLED.match(name)
     if m:
         flag = "" if m.group(4) is None else (", true" if m.group(4) == "1" else ", false")
-        name = f"pulbm::{m.group(1)}<{m.group(2)}, {_TYPES[m.group(3)]}{flag}>"
+        par = "" if m.group(5) is None else f", {m.group(5)}"
+        name = f"pulbm::{m.group(1)}<{m.group(2)}, {_TYPES[m.group(3)]}{flag}{par}>"
     name = name.replace("(anonymous namespace)::", "")
     name = re.sub(r"\(.*", "", name)
     return name.replace("void ", "")

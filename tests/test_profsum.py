@@ -9,6 +9,11 @@ def test_mangled_and_demangled_names_agree():
     assert short("_ZN5pulbm9k_momentsILi2EDF16_EEvNS_7CaseTabEPKii") == "pulbm::k_moments<2, _Float16>"
     assert short("void pulbm::k_collide<3, float, false>(pulbm::CaseTab, int const*, int)") == \
         "pulbm::k_collide<3, float, false>"
+    # the collide kernels of each step parity
+    assert short("_ZN5pulbm9k_collideILi3EDF16_Lb0ELi1EEEvPKPNS_7CaseDevEPKii") == \
+        "pulbm::k_collide<3, _Float16, false, 1>"
+    assert short("pulbm::k_collide<3, float, false, 0>(pulbm::CaseDev* const*, int const*, int)") == \
+        "pulbm::k_collide<3, float, false, 0>"
 
 
 def test_issue_summary_per_wave_and_issue_time(tmp_path):
