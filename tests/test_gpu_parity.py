@@ -58,6 +58,10 @@ CASES = {
     # the ragged last one cell by cell
     "3d_periodic_wide": dict(dim=3, nx=70, ny=9, nz=7),
     "3d_walls_y_wide": dict(dim=3, nx=130, ny=8, nz=6, wall=(0, 1, 0), gravity=(0.0, -1e-5, 0.0)),
+    # tiles clear of every edge (x origin 64, rows inside y and z): the odd
+    # steps' collide fixes their slots (and the edge tiles' decide them as
+    # they run)
+    "3d_periodic_long": dict(dim=3, nx=200, ny=12, nz=10),
     # full 64-node rows in tiles at walls on every axis: their halo rows are
     # read as vectors, ghost rows and end cells mirrored
     "3d_all_walls_full_rows": dict(dim=3, nx=128, ny=6, nz=5, wall=(1, 1, 1), gravity=(1e-6, 2e-6, -1e-5)),
@@ -173,7 +177,8 @@ def test_static_droplet_2d_config_full_run():
 
 
 @pytest.mark.parametrize("store,tol", [("fp32", 2e-5)])
-@pytest.mark.parametrize("case", ["3d_walls_z_gravity", "2d_walls_gravity", "3d_walls_y_wide", "3d_all_walls_full_rows"])
+@pytest.mark.parametrize("case", ["3d_walls_z_gravity", "2d_walls_gravity", "3d_walls_y_wide", "3d_all_walls_full_rows",
+                                  "3d_periodic_long"])
 def test_fp32_matches_oracle(store, tol, case):
     """FP32 storage element by element against the FP64 reference, without
     delta theta: its sign switch s = L phi / (|L phi| + eps) (Sec. II) is
@@ -351,7 +356,8 @@ def test_bgk_collision_matches_oracle(case, store, tol):
 
 @pytest.mark.parametrize("store,tol", [("fp64", TOL64), ("fp32", 2e-5)])
 @pytest.mark.parametrize("collision", ["filter", "bgk"])
-@pytest.mark.parametrize("case", ["3d_periodic_ragged", "3d_walls_z_gravity", "3d_all_walls", "3d_periodic_wide"])
+@pytest.mark.parametrize("case", ["3d_periodic_ragged", "3d_walls_z_gravity", "3d_all_walls", "3d_periodic_wide",
+                                  "3d_periodic_long"])
 def test_d3q19_hydro_matches_oracle(case, collision, store, tol):
     """D3Q19 for the hydrodynamic populations as well as the phase field
     (the lattice of the paper's 3D runs, Sec. II).  FP32 runs without delta
