@@ -91,6 +91,14 @@ struct CaseDev {
     uint32_t dvh[4], dvl[4];
     int32_t tile_rev;  // 1: the case's tiles are taken in reverse order (a race check, pulbm_set_tile_order)
     int32_t pad1;
+    // Constants of the collision derived once on the host (so no thread
+    // divides in FP64): 1 / tau_phi, M / (T W), 48 sigma / W, 1.5 sigma W;
+    // and every constant the FP32 kernels use, rounded once to FP32.
+    double inv_tau_phi, theta0, sig48W, sigW15;
+    struct {
+        float rho_a, drho, tau_a, dtau, inv_tau_phi, theta0, sig48W, sigW15, lambda_b, grav[3];
+        float h_scale, h_inv_scale, g_scale, g_inv_scale;
+    } f32;
 };
 
 using CDesc = const PULBM_CST CaseDev;
@@ -646,22 +654,29 @@ struct Phys {
     int delta_theta;
 };
 
+// A case constant in the compute type: the host's FP32 copy for FP32
+// arithmetic, the FP64 value otherwise.
+template <class CT> __device__ __forceinline__ CT cconst(double d, float f)
+{
+    if constexpr (std::is_same_v<CT, float>) return f;
+    else return (CT)d;
+}
+
 template <class CT>
 __device__ __forceinline__ Phys<CT> make_phys(CDesc& cs)
 {
     Phys<CT> p;
-    p.rho_a = (CT)cs.rho_a;
-    p.drho = (CT)(cs.rho_w - cs.rho_a);
-    p.tau_a = (CT)cs.tau_a;
-    p.dtau = (CT)(cs.tau_w - cs.tau_a);
-    p.inv_tau_phi = (CT)(1.0 / cs.tau_phi);
-    p.theta0 = (CT)(cs.M / (kT * cs.W));
-    p.sig48W = (CT)(48.0 * cs.sigma / cs.W);
-    p.sigW15 = (CT)(1.5 * cs.sigma * cs.W);
-    p.lambda_b = (CT)cs.lambda_b;
-    p.grav[0] = (CT)cs.grav[0];
-    p.grav[1] = (CT)cs.grav[1];
-    p.grav[2] = (CT)cs.grav[2];
+    p.rho_a = cconst<CT>(cs.rho_a, cs.f32.rho_a);
+    p.drho = cconst<CT>(cs.rho_w - cs.rho_a, cs.f32.drho);
+    p.tau_a = cconst<CT>(cs.tau_a, cs.f32.tau_a);
+    p.dtau = cconst<CT>(cs.tau_w - cs.tau_a, cs.f32.dtau);
+    p.inv_tau_phi = cconst<CT>(cs.inv_tau_phi, cs.f32.inv_tau_phi);
+    p.theta0 = cconst<CT>(cs.theta0, cs.f32.theta0);
+    p.sig48W = cconst<CT>(cs.sig48W, cs.f32.sig48W);
+    p.sigW15 = cconst<CT>(cs.sigW15, cs.f32.sigW15);
+    p.lambda_b = cconst<CT>(cs.lambda_b, cs.f32.lambda_b);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) p.grav[a] = cconst<CT>(cs.grav[a], cs.f32.grav[a]);
     p.delta_theta = cs.delta_theta;
     return p;
 }
@@ -973,7 +988,7 @@ __device__ __forceinline__ void moments_node(CDesc& cs, int x, int y, int z, boo
     const uint32_t nb = n * (uint32_t)sizeof(S);
     const Nav nv = make_nav(cs, x, y, z, (int)sizeof(S));
     const Slots<S> hs = slots<S>(cs.h, cs.N), gs = slots<S>(cs.g, cs.N);
-    const CT hsc = (CT)cs.h_inv_scale, gsc = (CT)cs.g_inv_scale;
+    const CT hsc = cconst<CT>(cs.h_inv_scale, cs.f32.h_inv_scale), gsc = cconst<CT>(cs.g_inv_scale, cs.f32.g_inv_scale);
     // 2-byte storage holds the populations less shifts made of phi (h) and
     // u (g) of this node one step earlier
     const CT php = h_reference<S>(cs.phi[odd ? 0 : 1], n);
@@ -1222,7 +1237,7 @@ __device__ __forceinline__ void velocity_tile(CDesc& cs, const TileCtx& t, CT* s
         for (int a = 0; a < DIMV; ++a) *Us.at(a, na) = 0;
         return;
     }
-    const CT ra = (CT)cs.rho_a, dr = (CT)(cs.rho_w - cs.rho_a);
+    const CT ra = cconst<CT>(cs.rho_a, cs.f32.rho_a), dr = cconst<CT>(cs.rho_w - cs.rho_a, cs.f32.drho);
     const CT rho = ra + clamp01(phi) * dr;
     const CT irho = rcp(rho);
     const int cx = lx + 1, cy = ly + 1, cz = lz + HR::ZH;
@@ -1431,7 +1446,8 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
     // the BGK collision needs the equilibria alone (no Pi: the INIT form)
     const NodeCoef<DIMV, CT> kc = node_coef<DIMV, BGK, CT>(ph, v, m2);
     const CT omf = BGK ? (CT)1 - rcp(ph.tau_a + clamp01(v.phi) * ph.dtau) : (CT)0;  // 1 - 1/tau_mix
-    const CT hisc = (CT)cs.h_inv_scale, hsc = (CT)cs.h_scale, gsc = (CT)cs.g_scale, gsc_in = (CT)cs.g_inv_scale;
+    const CT hisc = cconst<CT>(cs.h_inv_scale, cs.f32.h_inv_scale), hsc = cconst<CT>(cs.h_scale, cs.f32.h_scale);
+    const CT gsc = cconst<CT>(cs.g_scale, cs.f32.g_scale), gsc_in = cconst<CT>(cs.g_inv_scale, cs.f32.g_inv_scale);
     const CT corr = (CT)6.0 * rcp(kc.rho);  // 2 / (rho T)
     // shifts of an outgoing g_i and h_i in 2-byte storage, from phi and u
     // (this step) of the node that reads it next step: x + c_i, or x itself
@@ -1650,7 +1666,7 @@ __global__ __launch_bounds__(256) void k_init(CaseTab cases, const int* hdr,
     NodeVals<CT> v;
     tile_gradients<LS, R, CT>(sPhi, sRho, sU, lx + 1, ly + 1, lz + HR::ZH, v);
     const NodeCoef<DIMV, CT> kc = node_coef<DIMV, true, CT>(ph, v, (const CT*)nullptr);
-    const CT hsc = (CT)cs.h_scale, gsc = (CT)cs.g_scale;
+    const CT hsc = cconst<CT>(cs.h_scale, cs.f32.h_scale), gsc = cconst<CT>(cs.g_scale, cs.f32.g_scale);
     // 2-byte storage: h_j - w_j phi0 (the previous-step phi of step 0 is phi0)
     const CT phr = sizeof(S) == 2 ? v.phi : (CT)0;
     CT hmoved = 0;

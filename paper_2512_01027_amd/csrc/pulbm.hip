@@ -292,6 +292,32 @@ void codec_constants(const pulbm_params& p, CaseDev& h)
     }
 }
 
+// The collision's derived constants, once on the host, in the expressions
+// the kernels used (bitwise the values a thread would compute), and their
+// FP32 roundings.
+void derived_constants(CaseDev& h)
+{
+    h.inv_tau_phi = 1.0 / h.tau_phi;
+    h.theta0 = h.M / (kT * h.W);
+    h.sig48W = 48.0 * h.sigma / h.W;
+    h.sigW15 = 1.5 * h.sigma * h.W;
+    auto& f = h.f32;
+    f.rho_a = (float)h.rho_a;
+    f.drho = (float)(h.rho_w - h.rho_a);
+    f.tau_a = (float)h.tau_a;
+    f.dtau = (float)(h.tau_w - h.tau_a);
+    f.inv_tau_phi = (float)h.inv_tau_phi;
+    f.theta0 = (float)h.theta0;
+    f.sig48W = (float)h.sig48W;
+    f.sigW15 = (float)h.sigW15;
+    f.lambda_b = (float)h.lambda_b;
+    for (int a = 0; a < 3; ++a) f.grav[a] = (float)h.grav[a];
+    f.h_scale = (float)h.h_scale;
+    f.h_inv_scale = (float)h.h_inv_scale;
+    f.g_scale = (float)h.g_scale;
+    f.g_inv_scale = (float)h.g_inv_scale;
+}
+
 int upload_desc(pulbm_case* c)
 {
     HIPC(hipMemcpyAsync(c->d, &c->h, sizeof(CaseDev), hipMemcpyHostToDevice, c->stream));
@@ -425,6 +451,7 @@ extern "C" int pulbm_create(const pulbm_params* p, void* dev_arena, size_t arena
     h.fuse_u = !h.has_block && !p->wall[0] && !p->wall[1] && !p->wall[2] && store_bytes(p->store) >= 4 &&
                p->nx >= 3 && p->ny >= 3 && (p->dim == 2 || (p->nz >= 3 && p->q_hydro == 19));
     codec_constants(*p, h);
+    derived_constants(h);
     c->d = (CaseDev*)(c->base + L.desc);
     c->tab = (CaseDev**)(c->base + L.tab);
     c->hdr = (int*)(c->base + L.tab + sizeof(CaseDev*));
