@@ -973,7 +973,7 @@ struct pulbm_batch {
         hipEvent_t staged[2] = {nullptr, nullptr};
         int which = 0;
         int cap = 0, ncases = 0, tiles = 0, grid = 0;
-        std::map<int, hipGraphExec_t> graphs;  // by ksteps, captured for `grid` blocks
+        std::map<int, hipGraphExec_t> graphs;  // by 4 ksteps + parity (0, 1; 2 mixed), captured for `grid` blocks
     } tab[6];  // index (lattice set - 2) + 3 * collision
     bool dirty = true;
 };
@@ -1200,19 +1200,34 @@ extern "C" int pulbm_batch_advance(pulbm_batch* b, int32_t ksteps)
     for (int di = 0; di < 6; ++di) {
         pulbm_batch::Tab& t = b->tab[di];
         if (t.ncases == 0) continue;
-        auto it = t.graphs.find(ksteps);
+        // the step parity of the table's unfinished cases at this advance's
+        // first step: when they all agree (the usual case: cases start at step
+        // 0 and advance by the same k), each step launches the collide kernel
+        // of its parity only; when they differ, both (each skips the other's
+        // tiles).  Finished cases run nothing, whatever their parity.
+        int par = -2;
+        for (auto& s : b->slots)
+            if (s.c && s.c->step < s.end && lattice_set(s.c->p.dim, s.c->p.q_hydro) == di % 3 + 2 &&
+                s.c->p.collision == di / 3) {
+                const int p = (int)(s.c->step & 1);
+                par = par == -2 ? p : (par == p ? p : -1);
+            }
+        if (par == -2) par = 0;
+        const int key = ksteps * 4 + (par < 0 ? 2 : par);
+        auto it = t.graphs.find(key);
         if (it == t.graphs.end()) {
             hipGraph_t g = nullptr;
             hipGraphExec_t ge = nullptr;
             HIPC(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
             for (int k = 0; k < ksteps; ++k)
                 for (int w = 0; w < kStepKernels; ++w)
-                    launch(di % 3 + 2, b->store, di / 3 == 1, b->stream, t.dtab, t.dhdr, t.grid, k, w);
+                    launch(di % 3 + 2, b->store, di / 3 == 1, b->stream, t.dtab, t.dhdr, t.grid, k, w,
+                           par < 0 ? -1 : (par + k) & 1);
             hipLaunchKernelGGL(k_advance, dim3((t.cap + 63) / 64), dim3(64), 0, b->stream, t.dtab, t.dhdr, ksteps);
             HIPC(hipStreamEndCapture(b->stream, &g));
             HIPC(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
             (void)hipGraphDestroy(g);
-            it = t.graphs.emplace(ksteps, ge).first;
+            it = t.graphs.emplace(key, ge).first;
         }
         HIPC(hipGraphLaunch(it->second, b->stream));
     }

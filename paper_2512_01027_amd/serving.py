@@ -79,7 +79,8 @@ def _summary(reqs, makespan):
 
 def run_batched(reqs, hbm_budget: int, store: str = "fp16", k: int = 50, max_slots: int = 64,
                 fill_nodes: int = 12 << 20, admit_per_round: int = 4, policy: str = "fifo",
-                big_nodes: int = 3 << 19, fill_with_big: int | None = None, progress=None):
+                big_nodes: int = 3 << 19, fill_with_big: int | None = None, max_wait: float | None = None,
+                progress=None):
     """Continuous batching.  Returns the summary; sets each request's done.
 
     Waiting requests are admitted in arrival order ("fifo") or least work
@@ -97,7 +98,10 @@ def run_batched(reqs, hbm_budget: int, store: str = "fp16", k: int = 50, max_slo
     the large case, which every resident case slows as all of them advance
     in lock-step, keeps most of the GPU), and may overtake a large request
     that waits.  A small request then never queues behind a large one, and a
-    large one never shares the GPU with another large one.
+    large one never shares the GPU with another large one.  max_wait: a
+    small request that has waited longer than this (seconds) is admitted
+    past the fill limit, so that small requests arriving in a burst beside a
+    long large case do not wait for it.
 
     progress(finished, total, elapsed), when given, is called after every
     completion.
@@ -133,7 +137,8 @@ def run_batched(reqs, hbm_budget: int, store: str = "fp16", k: int = 50, max_slo
                     i_w += 1  # waits; later small requests may pass it
                     continue
                 cap = fill_with_big if big_resident else fill_nodes
-                if not big and small_held and small_held + r.nodes > cap:
+                aged = max_wait is not None and now - r.arrival > max_wait
+                if not big and small_held and small_held + r.nodes > cap and not aged:
                     i_w += 1
                     continue
                 slot = bt.admit(r.cfg, *r.fields, r.steps)
@@ -175,7 +180,7 @@ def run_batched(reqs, hbm_budget: int, store: str = "fp16", k: int = 50, max_slo
     out = _summary(reqs, makespan)
     out.update({"peak_resident": peak, "advance_steps": k, "fill_nodes": fill_nodes, "policy": policy})
     if policy == "big_fifo":
-        out.update({"big_nodes": big_nodes, "fill_with_big": fill_with_big})
+        out.update({"big_nodes": big_nodes, "fill_with_big": fill_with_big, "max_wait": max_wait})
     return out
 
 
@@ -236,6 +241,7 @@ def main(argv=None):
     ap.add_argument("--policy", default="big_fifo")
     ap.add_argument("--fill-nodes", type=int, default=4 << 20)
     ap.add_argument("--fill-with-big", type=int, default=1 << 20)
+    ap.add_argument("--max-wait", type=float, default=None)
     ap.add_argument("--k", type=int, default=50)
     ap.add_argument("--budget-frac", type=float, default=0.8)
     ap.add_argument("--out", required=True)
@@ -273,7 +279,7 @@ def main(argv=None):
 
     if a.mode == "batched":
         res = run_batched(reqs, budget, k=a.k, policy=a.policy, fill_nodes=a.fill_nodes,
-                          fill_with_big=a.fill_with_big, progress=progress)
+                          fill_with_big=a.fill_with_big, max_wait=a.max_wait, progress=progress)
     else:
         res = run_sequential(reqs, progress=progress)
     out["summary"] = res

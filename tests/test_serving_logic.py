@@ -127,6 +127,36 @@ def test_big_fifo_smaller_fill_beside_a_large_case(fake):
     assert all(not math.isnan(r.done) for r in reqs)
 
 
+def test_big_fifo_admits_a_small_request_past_the_fill_limit_after_max_wait(fake, monkeypatch):
+    """Beside a large case the small-case fill is fill_with_big; a small
+    request that has waited longer than max_wait is admitted past it."""
+    clock = [0.0]
+    monkeypatch.setattr(SV.time, "perf_counter", lambda: clock[0])
+    orig_advance = FakeBatch.advance
+
+    def advance(self, k):
+        clock[0] += 1.0  # one second per advance
+        orig_advance(self, k)
+
+    monkeypatch.setattr(FakeBatch, "advance", advance)
+    reqs = _reqs([(500, 1000)] + [(10, 400)] * 3)
+    for r in reqs:
+        r.arrival = 0.0
+    SV.run_batched(reqs, hbm_budget=10 ** 9, k=50, fill_nodes=40, fill_with_big=10, admit_per_round=8,
+                   policy="big_fifo", big_nodes=400, max_wait=2.5)
+    log = [e for e in fake.log if e[0] == "admit"]
+    # the large case and one small one at once; the others only once they
+    # have waited past max_wait (3 advances), with the large case still running
+    first = [e for e in log if e[1] in (0, 1)]
+    assert len(first) == 2
+    late = [e for e in log if e[1] in (2, 3)]
+    assert len(late) == 2 and all(500 in e[2] for e in late)
+    # past max_wait both join the first small case (without the bound they
+    # would wait for it to finish, one at a time)
+    assert any(e[2] == [10, 10, 10, 500] for e in late)
+    assert all(not math.isnan(r.done) for r in reqs)
+
+
 def test_fill_limit_and_refusals(fake):
     reqs = _reqs([(60, 100)] * 6 + [(250, 50)])
     orig_init = FakeBatch.__init__
