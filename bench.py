@@ -224,12 +224,13 @@ def serving_leg(n_cases=64, step_scale=0.1):
     free, _ = torch.cuda.mem_get_info()
     budget = int(0.8 * free)
     SV.set_arrivals(reqs, None)
-    burst_b = SV.run_batched(reqs, budget, policy="big_fifo", fill_nodes=4 << 20, fill_with_big=1 << 20)
+    pol = dict(policy="big_fifo", fill_nodes=4 << 20, fill_with_big=1 << 20, max_wait=6.0 * step_scale)
+    burst_b = SV.run_batched(reqs, budget, **pol)
     SV.set_arrivals(reqs, None)
     burst_s = SV.run_sequential(reqs)
     rate = 0.8 * burst_b["MLUPS"] * 1e6 / mean_work
     SV.set_arrivals(reqs, rate)
-    pois_b = SV.run_batched(reqs, budget, policy="big_fifo", fill_nodes=4 << 20, fill_with_big=1 << 20)
+    pois_b = SV.run_batched(reqs, budget, **pol)
     SV.set_arrivals(reqs, rate)
     pois_s = SV.run_sequential(reqs)
     small = SV.make_stream(n_cases, "fp16", step_scale, case_seed=4, max_nodes=64 ** 3)
@@ -245,7 +246,7 @@ def serving_leg(n_cases=64, step_scale=0.1):
                        f"{budget / 2**30:.0f} GiB; saturated: all at t=0; poisson: arrivals (seed 2) at "
                        f"{rate:.2f}/s = 0.8 x batched capacity / mean work; batched admission big_fifo (cases "
                        f"of 1.5M nodes or more one at a time, smaller ones alongside up to 4M nodes, 1M beside a "
-                       f"large one); "
+                       f"large one unless waiting longer than {6.0 * step_scale:.1f} s); "
                        f"small_cases: {n_cases} requests (seed 4) of at most 64^3 nodes, all at t=0, FIFO")}
 
 

@@ -241,7 +241,7 @@ def main(argv=None):
     ap.add_argument("--policy", default="big_fifo")
     ap.add_argument("--fill-nodes", type=int, default=4 << 20)
     ap.add_argument("--fill-with-big", type=int, default=1 << 20)
-    ap.add_argument("--max-wait", type=float, default=None)
+    ap.add_argument("--max-wait", type=float, default=6.0)
     ap.add_argument("--k", type=int, default=50)
     ap.add_argument("--budget-frac", type=float, default=0.8)
     ap.add_argument("--out", required=True)
