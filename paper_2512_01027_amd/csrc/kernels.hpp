@@ -700,7 +700,9 @@ struct NodeCoef {
     CT av[3];            // u + F / rho + sigma . grad rho / rho^2
     CT gbase;            // B div / T - u^2 / (2T)
     CT Bdiv;
-    CT kPi[3][3], kTr;   // (1 - 1/tau) / (2 T^2) * Pi, and * T tr(Pi)
+    // (1 - 1/tau) / (2 T^2) * Pi: its diagonal, twice its off-diagonal
+    // entries (xy, xz, yz), and * T tr(Pi)
+    CT kPi[3], kPi2[3], kTr;
 };
 
 template <int DIMV, bool INIT, class CT>
@@ -744,9 +746,9 @@ __device__ __forceinline__ NodeCoef<DIMV, CT> node_coef(const Phys<CT>& p, const
     k.rho = rho;
 #pragma unroll
     for (int a = 0; a < 3; ++a) k.F[a] = a < D ? rho * p.grav[a] + mu * v.gphi[a] : (CT)0;
-    CT div = 0;
+    CT div = v.G[0][0];
 #pragma unroll
-    for (int a = 0; a < D; ++a) div += v.G[a][a];
+    for (int a = 1; a < D; ++a) div += v.G[a][a];
     const CT bulk = rho * (CT)(2.0 / 3.0) * (p.lambda_b - nu) * div;
     const CT rnu = rho * nu;
 #pragma unroll
@@ -765,36 +767,49 @@ __device__ __forceinline__ NodeCoef<DIMV, CT> node_coef(const Phys<CT>& p, const
     k.Bdiv = B * div;
     k.gbase = k.Bdiv * iT - u2 * i2T;
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) k.kPi[a][b] = 0;
+    for (int a = 0; a < 3; ++a) k.kPi[a] = k.kPi2[a] = 0;
     k.kTr = 0;
     if (!INIT) {
-        // Pi = sum c c (g - g^eq) = M2 - (u u + B div I) on these lattices
-        CT Pi[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-        if (D == 2) {
-            Pi[0][0] = M2[0] - v.u[0] * v.u[0] - k.Bdiv;
-            Pi[1][1] = M2[1] - v.u[1] * v.u[1] - k.Bdiv;
-            Pi[0][1] = Pi[1][0] = M2[2] - v.u[0] * v.u[1];
-        } else {
-            Pi[0][0] = M2[0] - v.u[0] * v.u[0] - k.Bdiv;
-            Pi[1][1] = M2[1] - v.u[1] * v.u[1] - k.Bdiv;
-            Pi[2][2] = M2[2] - v.u[2] * v.u[2] - k.Bdiv;
-            Pi[0][1] = Pi[1][0] = M2[3] - v.u[0] * v.u[1];
-            Pi[0][2] = Pi[2][0] = M2[4] - v.u[0] * v.u[2];
-            Pi[1][2] = Pi[2][1] = M2[5] - v.u[1] * v.u[2];
+        // Pi = sum c c (g - g^eq) = M2 - (u u + B div I) on these lattices;
+        // diagonal entries, then xy, xz, yz (M2 holds xx, yy, [zz,] xy[, xz, yz])
+        CT Pd[3] = {0, 0, 0}, Po[3] = {0, 0, 0};
+#pragma unroll
+        for (int a = 0; a < D; ++a) Pd[a] = M2[a] - v.u[a] * v.u[a] - k.Bdiv;
+        Po[0] = M2[D] - v.u[0] * v.u[1];
+        if (D == 3) {
+            Po[1] = M2[4] - v.u[0] * v.u[2];
+            Po[2] = M2[5] - v.u[1] * v.u[2];
         }
         const CT kf = ((CT)1 - rcp(tau)) * i2T2;
-        CT tr = 0;
+        CT tr = Pd[0];
 #pragma unroll
-        for (int a = 0; a < D; ++a) tr += Pi[a][a];
+        for (int a = 1; a < D; ++a) tr += Pd[a];
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int b = 0; b < 3; ++b) k.kPi[a][b] = kf * Pi[a][b];
+        for (int a = 0; a < 3; ++a) {
+            k.kPi[a] = kf * Pd[a];
+            k.kPi2[a] = (kf + kf) * Po[a];
+        }
         k.kTr = kf * T * tr;
     }
     return k;
+}
+
+// c_i . x over the axes where direction j of lattice L is nonzero, started
+// from the first such term: an accumulator started at zero costs one more
+// add per sum (0 + x is not x when x is -0, so the compiler keeps the add).
+template <class L, int D, class CT>
+__device__ __forceinline__ CT c_dot(int j, const CT* x)
+{
+    CT s = 0;
+    bool first = true;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const int c = L::c(j, a);
+        if (c == 0) continue;
+        s = first ? (c == 1 ? x[a] : -x[a]) : (c == 1 ? s + x[a] : s - x[a]);
+        first = false;
+    }
+    return s;
 }
 
 // h^eq_j (INIT) or the BGK post-collision h*_j from the incoming h_j.
@@ -802,15 +817,37 @@ template <class H, int D, bool INIT, class CT>
 __device__ __forceinline__ CT h_out(const Phys<CT>& p, const NodeVals<CT>& v, const NodeCoef<D, CT>& k, int j,
                                     CT hj)
 {
-    CT cu = 0, cn = 0;
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-        if (H::c(j, a) == 1) { cu += v.u[a]; cn += k.nv[a]; }
-        if (H::c(j, a) == -1) { cu -= v.u[a]; cn -= k.nv[a]; }
-    }
+    const CT cu = c_dot<H, D>(j, v.u), cn = c_dot<H, D>(j, k.nv);
     const CT wj = (CT)H::w(j);
     const CT heq = wj * (v.phi * (k.base_h + cu * (CT)3.0 + cu * cu * (CT)4.5) + k.theta * cn);
     return INIT ? heq : hj + (heq - hj) * p.inv_tau_phi;
+}
+
+// The part of g^eq_i (INIT) or of the filtered g*_i that is even in c_i,
+// before the weight: 4.5 (c_i.u)^2 + B div u / T - u^2 / (2T), and when
+// filtered c_i.kPi.c_i - T tr(kPi).  c_i.kPi.c_i is summed as the diagonal
+// entries of the axes c_i spans, then the off-diagonal ones (kPi2 = 2 kPi),
+// so that directions spanning the same axes share one diagonal sum.
+template <class G, int D, bool INIT, class CT>
+__device__ __forceinline__ CT g_even(const NodeCoef<D, CT>& k, int i, CT cu)
+{
+    CT e = k.gbase;
+    if (!INIT) {
+        e = e - k.kTr;
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+            if (G::c(i, a) != 0) e = e + k.kPi[a];
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int b = a + 1; b < D; ++b) {
+                const int cc = G::c(i, a) * G::c(i, b);
+                const CT p2 = k.kPi2[a + b - 1];  // (0,1) -> 0, (0,2) -> 1, (1,2) -> 2
+                if (cc == 1) e = e + p2;
+                if (cc == -1) e = e - p2;
+            }
+    }
+    return cu * cu * (CT)4.5 + e;
 }
 
 // g^eq_i (INIT) or the filtered post-collision g*_i; the rest entry excludes
@@ -819,46 +856,25 @@ template <class G, int D, bool INIT, class CT>
 __device__ __forceinline__ CT g_out(const NodeVals<CT>& v, const NodeCoef<D, CT>& k, int i)
 {
     const CT wi = (CT)G::w(i);
-    CT ca = 0, cu = 0;
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-        if (G::c(i, a) == 1) { ca += k.av[a]; cu += v.u[a]; }
-        if (G::c(i, a) == -1) { ca -= k.av[a]; cu -= v.u[a]; }
-    }
-    CT inner = ca * (CT)3.0 + cu * cu * (CT)4.5 + k.gbase;
-    if (!INIT) {
-        CT cPc = 0;
-#pragma unroll
-        for (int a = 0; a < D; ++a)
-#pragma unroll
-            for (int b = 0; b < D; ++b) {
-                const int cc = G::c(i, a) * G::c(i, b);
-                if (cc == 1) cPc += k.kPi[a][b];
-                if (cc == -1) cPc -= k.kPi[a][b];
-            }
-        inner += cPc - k.kTr;
-    }
-    CT geq = wi * inner;
+    const CT ca = c_dot<G, D>(i, k.av), cu = c_dot<G, D>(i, v.u);
+    CT geq = wi * (g_even<G, D, INIT>(k, i, cu) + ca * (CT)3.0);
     if (i == 0) geq -= k.Bdiv * (CT)3.0;
     return geq;
 }
 
 // Opposite directions i and i+1 (i odd) have c_{i+1} = -c_i: the terms odd in
 // c change sign and the even ones do not, so each pair shares one evaluation.
+// The products of the weight with per-node values (w phi, w theta, ...) are
+// written alike in every pair, so directions of one weight share them.
 // h^eq (INIT) or the BGK post-collision h* for the pair (j, j+1).
 template <class H, int D, bool INIT, class CT>
 __device__ __forceinline__ void h_pair(const Phys<CT>& p, const NodeVals<CT>& v, const NodeCoef<D, CT>& k,
                                        int j, CT hj, CT hk, CT* oj, CT* ok)
 {
-    CT cu = 0, cn = 0;
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-        if (H::c(j, a) == 1) { cu += v.u[a]; cn += k.nv[a]; }
-        if (H::c(j, a) == -1) { cu -= v.u[a]; cn -= k.nv[a]; }
-    }
-    const CT wj = (CT)H::w(j);
-    const CT even = wj * v.phi * (k.base_h + cu * cu * (CT)4.5);
-    const CT odd = wj * (v.phi * cu * (CT)3.0 + k.theta * cn);
+    const CT cu = c_dot<H, D>(j, v.u), cn = c_dot<H, D>(j, k.nv);
+    const CT pw = (CT)H::w(j) * v.phi;
+    const CT even = cu * cu * (pw * (CT)4.5) + pw * k.base_h;
+    const CT odd = cu * (pw * (CT)3.0) + ((CT)H::w(j) * k.theta) * cn;
     const CT ej = even + odd, ek = even - odd;
     *oj = INIT ? ej : hj + (ej - hj) * p.inv_tau_phi;
     *ok = INIT ? ek : hk + (ek - hk) * p.inv_tau_phi;
@@ -869,28 +885,11 @@ template <class G, int D, bool INIT, class CT>
 __device__ __forceinline__ void g_pair(const NodeVals<CT>& v, const NodeCoef<D, CT>& k, int i, CT* oi, CT* ok)
 {
     const CT wi = (CT)G::w(i);
-    CT ca = 0, cu = 0;
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-        if (G::c(i, a) == 1) { ca += k.av[a]; cu += v.u[a]; }
-        if (G::c(i, a) == -1) { ca -= k.av[a]; cu -= v.u[a]; }
-    }
-    CT even = cu * cu * (CT)4.5 + k.gbase;
-    if (!INIT) {
-        CT cPc = 0;
-#pragma unroll
-        for (int a = 0; a < D; ++a)
-#pragma unroll
-            for (int b = 0; b < D; ++b) {
-                const int cc = G::c(i, a) * G::c(i, b);
-                if (cc == 1) cPc += k.kPi[a][b];
-                if (cc == -1) cPc -= k.kPi[a][b];
-            }
-        even += cPc - k.kTr;
-    }
-    const CT odd = ca * (CT)3.0;
-    *oi = wi * (even + odd);
-    *ok = wi * (even - odd);
+    const CT ca = c_dot<G, D>(i, k.av), cu = c_dot<G, D>(i, v.u);
+    const CT we = wi * g_even<G, D, INIT>(k, i, cu);
+    const CT w3 = wi * (CT)3.0;
+    *oi = ca * w3 + we;
+    *ok = we - ca * w3;
 }
 
 // Isotropic central differences (Sec. II) of a tile field at cell (cx,cy,cz):
@@ -943,17 +942,6 @@ __device__ __forceinline__ CT h_reference(void* phi_prev, uint32_t n)
 // step before: w_j phi for h, w_i c_i.u / T for g (T = 1/3).  Writer and
 // reader evaluate one expression on the same FP32 values, so the reader's
 // decode of a value equals the writer's own decode of it.
-template <class L, int D, class CT>
-__device__ __forceinline__ CT c_dot(int j, const CT* u)
-{
-    CT cu = 0;
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-        if (L::c(j, a) == 1) cu += u[a];
-        if (L::c(j, a) == -1) cu -= u[a];
-    }
-    return cu;
-}
 template <class CT> __device__ __forceinline__ CT g_shift(CT w, CT cu) { return (w * (CT)3) * cu; }
 // shift of an incoming g_i read by a node whose previous-step velocity is u
 template <class G, int D, class CT>
