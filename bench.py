@@ -74,17 +74,20 @@ def kernel_bytes(store_bytes, aux_bytes=4, pops=46, dim=3, q_phase=19):
     width, each read or written once): moments reads the populations and
     writes phi, u*(dim), P*, M2 (6 in 3D); pressure reads P*, u*, phi and
     writes P; velocity reads P, u*, phi and writes u; collide reads phi, u,
-    M2 and h and writes every population.  2-byte storage also reads the
-    previous-step phi in moments and collide (the h codec's reference) and the
-    previous-step u in moments (the g codec's reference)."""
+    M2 and h and writes every population.  2-byte storage keeps M2 in two
+    bytes per value (two to a 32-bit word, 4 bytes for the 3 values in 2D),
+    and also reads the previous-step phi in moments and collide (the h
+    codec's reference) and the previous-step u in moments (the g codec's
+    reference)."""
     ref = aux_bytes if store_bytes == 2 else 0
     uref = dim * aux_bytes if store_bytes == 2 else 0
     nm = 6 if dim == 3 else 3
+    m2 = 4 * ((nm + 1) // 2) if store_bytes == 2 else nm * aux_bytes
     return {
-        "moments": pops * store_bytes + ref + uref + (2 + dim + nm) * aux_bytes,
+        "moments": pops * store_bytes + ref + uref + (2 + dim) * aux_bytes + m2,
         "pressure": (3 + dim) * aux_bytes,
         "velocity": (2 + 2 * dim) * aux_bytes,
-        "collide": q_phase * store_bytes + ref + (1 + dim + nm) * aux_bytes + pops * store_bytes,
+        "collide": q_phase * store_bytes + ref + (1 + dim) * aux_bytes + m2 + pops * store_bytes,
     }
 
 

@@ -261,6 +261,21 @@ template <class T> __device__ __forceinline__ Slots<T> slots(void* p, int64_t N)
     return s;
 }
 
+// M2, the second moment of g that the moment stage writes and the collision
+// reads once, is kept in the compute type, except in 2-byte storage: there
+// each component is encoded with g's codec and scale (no shift) and two of
+// them share a 32-bit word (word j holds components 2j and 2j + 1, the first
+// in the low half), so a node's six values take three loads and three
+// registers.
+template <class S> __device__ __forceinline__ uint32_t m2_pack(S lo, S hi)
+{
+    return (uint32_t)__builtin_bit_cast(uint16_t, lo) | ((uint32_t)__builtin_bit_cast(uint16_t, hi) << 16);
+}
+template <class S> __device__ __forceinline__ S m2_half(uint32_t w, int k)
+{
+    return __builtin_bit_cast(S, (uint16_t)(k ? w >> 16 : w & 0xffffu));
+}
+
 template <class T> __device__ __forceinline__ PULBM_GLB T* at_node(void* p, uint32_t n)
 {
     return (PULBM_GLB T*)((PULBM_GLB char*)p + n * (uint32_t)sizeof(T));
@@ -1016,15 +1031,27 @@ __device__ __forceinline__ void moments_node(CDesc& cs, int x, int y, int z, boo
     }
     const uint32_t na = n * (uint32_t)sizeof(CT);
     *at_node<CT>(cs.phi[odd ? 1 : 0], n) = phi;
-    const Slots<CT> Js = slots<CT>(cs.J, cs.N), Ms = slots<CT>(cs.M2, cs.N);
+    const Slots<CT> Js = slots<CT>(cs.J, cs.N);
 #pragma unroll
     for (int a = 0; a < DIMV; ++a) *Js.at(a, na) = J[a];
     using AT = CT;
     const double Pprev = (double)*at_node<AT>(cs.P[odd ? 1 : 0], n);
     *at_node<AT>(cs.Ps, n) = (AT)(Pprev + cs.rho_a * kT * (double)sum);
     constexpr int NM = DIMV == 2 ? 3 : 6;
+    if constexpr (sizeof(S) == 2) {
+        const Slots<uint32_t> Ms = slots<uint32_t>(cs.M2, cs.N);
+        const CT gsc_out = cconst<CT>(cs.g_scale, cs.f32.g_scale);
 #pragma unroll
-    for (int k = 0; k < NM; ++k) *Ms.at(k, na) = m2[k];
+        for (int j = 0; j < (NM + 1) / 2; ++j) {
+            const S lo = Codec<S>::enc(m2[2 * j], gsc_out, (CT)0);
+            const S hi = 2 * j + 1 < NM ? Codec<S>::enc(m2[2 * j + 1], gsc_out, (CT)0) : (S)0;
+            *Ms.at(j, n * 4u) = m2_pack<S>(lo, hi);
+        }
+    } else {
+        const Slots<CT> Ms = slots<CT>(cs.M2, cs.N);
+#pragma unroll
+        for (int k = 0; k < NM; ++k) *Ms.at(k, na) = m2[k];
+    }
 }
 
 template <int LS, class S>
@@ -1048,11 +1075,19 @@ __global__ __launch_bounds__(256) void k_moments(CaseTab cases, const int* hdr, 
             const uint32_t na = n * (uint32_t)sizeof(CT);
             *at_node<CT>(cs.phi[odd ? 1 : 0], n) = 0;
             *at_node<CT>(cs.Ps, n) = 0;
-            const Slots<CT> Js = slots<CT>(cs.J, cs.N), Ms = slots<CT>(cs.M2, cs.N);
+            const Slots<CT> Js = slots<CT>(cs.J, cs.N);
 #pragma unroll
             for (int a = 0; a < DIMV; ++a) *Js.at(a, na) = 0;
+            constexpr int NM = DIMV == 2 ? 3 : 6;
+            if constexpr (sizeof(S) == 2) {
+                const Slots<uint32_t> Ms = slots<uint32_t>(cs.M2, cs.N);
 #pragma unroll
-            for (int k = 0; k < (DIMV == 2 ? 3 : 6); ++k) *Ms.at(k, na) = 0;
+                for (int j = 0; j < (NM + 1) / 2; ++j) *Ms.at(j, n * 4u) = 0u;  // +0 in both halves
+            } else {
+                const Slots<CT> Ms = slots<CT>(cs.M2, cs.N);
+#pragma unroll
+                for (int k = 0; k < NM; ++k) *Ms.at(k, na) = 0;
+            }
             return;
         }
         moments_node<LS, S, true>(cs, x, y, z, odd);
@@ -1318,7 +1353,7 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
     // block nodes carry no fluid and are skipped like nodes past the grid
     const bool inside = x < cs.nx && y < cs.ny && z < cs.nz && !(WALL && in_block(cs, x, y, z));
     const uint32_t n = inside ? (uint32_t)x + (uint32_t)cs.sx * ((uint32_t)y + (uint32_t)cs.ny * (uint32_t)z) : 0u;
-    const uint32_t nb = n * (uint32_t)sizeof(S), na = n * (uint32_t)sizeof(CT);
+    const uint32_t nb = n * (uint32_t)sizeof(S), na = n * (uint32_t)(sizeof(S) == 2 ? 4 : sizeof(CT));
     // the step's parity, which decides the slots the AA pattern reads and
     // writes.  PAR 0: even, fixed at compile time.  PAR 1: odd, read again at
     // run time (step_parity), so that each load and store decides its slot
@@ -1337,7 +1372,10 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
     const Slots<S> hs = slots<S>(cs.h, cs.N), gs = slots<S>(cs.g, cs.N);
     // own-node loads first
     S hraw[H::Q];
-    CT m2[NM];
+    // M2 as loaded: compute-type values, or words of two 2-byte codes
+    using M2L = std::conditional_t<sizeof(S) == 2, uint32_t, CT>;
+    constexpr int NL = sizeof(S) == 2 ? (NM + 1) / 2 : NM;
+    M2L m2l[NL];
     CT php = 0;  // reference of the incoming h (2-byte storage)
     CT dP = 0;   // BGK: (previous P - new P) / (rho_ref T), restores the stored rest population
     CT ur[3] = {0, 0, 0};  // BGK, 2-byte storage: reference of the incoming g
@@ -1350,9 +1388,9 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
             dP = (CT)(((double)*at_node<CT>(cs.P[t.step & 1], n) - (double)*at_node<CT>(cs.P[(t.step + 1) & 1], n)) *
                       (3.0 / cs.rho_a));
         } else {
-            const Slots<CT> Ms = slots<CT>(cs.M2, cs.N);
+            const Slots<M2L> Ms = slots<M2L>(cs.M2, cs.N);
 #pragma unroll
-            for (int k = 0; k < NM; ++k) m2[k] = *Ms.at(k, na);
+            for (int k = 0; k < NL; ++k) m2l[k] = *Ms.at(k, na);
         }
     }
     // 2-byte storage parks h in LDS before the halo loads: the codec's extra
@@ -1429,6 +1467,17 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
     }
     if (!inside) return;
 
+    CT m2[NM];
+    if constexpr (!BGK) {
+        if constexpr (sizeof(S) == 2) {
+            const CT gsc_m = cconst<CT>(cs.g_inv_scale, cs.f32.g_inv_scale);
+#pragma unroll
+            for (int k = 0; k < NM; ++k) m2[k] = Codec<S>::dec(m2_half<S>(m2l[k / 2], k & 1), gsc_m, (CT)0);
+        } else {
+#pragma unroll
+            for (int k = 0; k < NM; ++k) m2[k] = m2l[k];
+        }
+    }
     NodeVals<CT> v;
     tile_gradients<LS, R, CT>(sPhi, sRho, sU, lx + 1, ly + 1, lz + HR::ZH, v);
     // the BGK collision needs the equilibria alone (no Pi: the INIT form)

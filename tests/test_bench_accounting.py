@@ -30,9 +30,13 @@ def test_fp32_d3q27_bytes_per_node():
 def test_fp16_bytes_per_node():
     kb = bench.kernel_bytes(2)
     # the 2-byte codecs read the previous step's phi (4 B) in both kernels
-    # and the previous step's u (12 B) in moments
-    assert kb["moments"] == 46 * 2 + 4 + 12 + 44 == 152
-    assert kb["collide"] == 19 * 2 + 4 + 40 + 46 * 2 == 174
+    # and the previous step's u (12 B) in moments; M2's six values take two
+    # bytes each (phi, u*, P* stay 4-byte: 20 B)
+    assert kb["moments"] == 46 * 2 + 4 + 12 + 20 + 12 == 140
+    assert kb["collide"] == 19 * 2 + 4 + 16 + 12 + 46 * 2 == 162
+    # 2D: three M2 values in two 32-bit words
+    kb2 = bench.kernel_bytes(2, pops=18, dim=2, q_phase=9)
+    assert kb2["moments"] == 18 * 2 + 4 + 8 + 16 + 8
 
 
 def test_d3q19_hydro_populations():
