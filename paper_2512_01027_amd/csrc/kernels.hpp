@@ -401,10 +401,12 @@ __device__ __forceinline__ bool tile_at_wall(CDesc& cs, int ox, int oy, int oz)
 // caches, so accesses can be marked non-temporal.  Which accesses gain from it
 // was measured per storage width (bit 0: loads in k_moments, bit 1: loads in
 // k_collide, bit 2: stores in k_collide): 4- and 8-byte populations stream
-// their loads, 2-byte populations the collide's loads and stores (streaming
-// k_moments' 2-byte loads too speeds its even steps and slows its odd ones).
-enum PopAccess { kLoadMoments = 1, kLoadCollide = 2, kStoreCollide = 4 };
-constexpr int kNtWide = kLoadMoments | kLoadCollide, kNtHalf = kLoadCollide | kStoreCollide;
+// their loads; 2-byte populations the collide's loads and stores, and
+// k_moments' loads on even steps only (bit 3): on odd steps, shifted by one
+// node in x, a 128-byte line is read half by one tile and half by its x
+// neighbour, and streamed past L2 it is fetched twice.
+enum PopAccess { kLoadMoments = 1, kLoadCollide = 2, kStoreCollide = 4, kLoadMomentsEven = 8 };
+constexpr int kNtWide = kLoadMoments | kLoadCollide, kNtHalf = kLoadCollide | kStoreCollide | kLoadMomentsEven;
 template <class S, int A> constexpr bool nt_access() { return ((sizeof(S) >= 4 ? kNtWide : kNtHalf) & A) != 0; }
 
 // Population arriving at the node (byte offset nb) along direction i.
@@ -980,7 +982,7 @@ __device__ __forceinline__ void u_reference(void* u_prev, int64_t N, uint32_t n,
 }
 
 // --- moments: phi, u* = sum g c, P*, M2 (per node; no halo)
-template <int LS, class S, bool WALL>
+template <int LS, class S, bool WALL, bool NTL>
 __device__ __forceinline__ void moments_node(CDesc& cs, int x, int y, int z, bool odd)
 {
     constexpr int DIMV = Model<LS>::DIM;
@@ -1001,12 +1003,12 @@ __device__ __forceinline__ void moments_node(CDesc& cs, int x, int y, int z, boo
     CT phi = 0;
 #pragma unroll
     for (int j = 0; j < H::Q; ++j)
-        phi += Codec<S>::dec(aa_load<H, WALL, nt_access<S, kLoadMoments>()>(hs, nb, nv, j, odd), hsc,
+        phi += Codec<S>::dec(aa_load<H, WALL, NTL>(hs, nb, nv, j, odd), hsc,
                              php * (CT)H::w(j));
     CT sum = 0, J[3] = {0, 0, 0}, m2[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
     for (int i = 0; i < G::Q; ++i) {
-        const CT f = Codec<S>::dec(aa_load<G, WALL, nt_access<S, kLoadMoments>()>(gs, nb, nv, i, odd), gsc,
+        const CT f = Codec<S>::dec(aa_load<G, WALL, NTL>(gs, nb, nv, i, odd), gsc,
                                    g_ref<G, DIMV>(i, ur));
         sum += f;
 #pragma unroll
@@ -1070,6 +1072,8 @@ __global__ __launch_bounds__(256) void k_moments(CaseTab cases, const int* hdr, 
     const int x = t.ox + lx, y = t.oy + ly, z = t.oz + lz;
     if (x >= cs.nx || y >= cs.ny || z >= cs.nz) return;
     const bool odd = t.step & 1;
+    constexpr bool nt_odd = nt_access<S, kLoadMoments>();
+    constexpr bool nt_even = nt_odd || nt_access<S, kLoadMomentsEven>();
     if (tile_at_wall<Mo>(cs, t.ox, t.oy, t.oz)) {
         if (in_block(cs, x, y, z)) {
             // block nodes carry no fluid: phi, u*, P*, M2 = 0
@@ -1094,9 +1098,11 @@ __global__ __launch_bounds__(256) void k_moments(CaseTab cases, const int* hdr, 
             }
             return;
         }
-        moments_node<LS, S, true>(cs, x, y, z, odd);
+        if (odd) moments_node<LS, S, true, nt_odd>(cs, x, y, z, true);
+        else moments_node<LS, S, true, nt_even>(cs, x, y, z, false);
     } else {
-        moments_node<LS, S, false>(cs, x, y, z, odd);
+        if (odd) moments_node<LS, S, false, nt_odd>(cs, x, y, z, true);
+        else moments_node<LS, S, false, nt_even>(cs, x, y, z, false);
     }
 }
 
