@@ -454,6 +454,14 @@ template <int RX, int RY, int RZ>
 struct Region {
     static constexpr int N = RX * RY * RZ;
     __device__ static __forceinline__ int idx(int ix, int iy, int iz) { return ix + RX * (iy + RY * iz); }
+    // The 3x3(x3) neighbourhood of cell (cx, cy, cz): its lowest corner
+    // (cx - 1, cy - 1, cz - ZL) as a base index, and each cell of it at a
+    // constant offset from there that is never negative, which LDS reads
+    // take as their immediate (DS offsets are unsigned).
+    template <int ZL>
+    __device__ static __forceinline__ int nb_base(int cx, int cy, int cz) { return idx(cx - 1, cy - 1, cz - ZL); }
+    template <int ZL>
+    static constexpr int nb(int dx, int dy, int dz) { return (1 + dx) + RX * ((1 + dy) + RY * (ZL + dz)); }
 };
 
 // 1-halo region of a tile: cell k -> mirror node index, wall offsets, crossings.
@@ -1169,8 +1177,8 @@ __device__ __forceinline__ void pressure_tile(CDesc& cs, const TileCtx& t, AT* s
     // the auxiliary type)
     const double drho = (double)clamp01(phi) * (cs.rho_w - cs.rho_a);
     const double rho = cs.rho_a + drho;
-    const int cx = lx + 1, cy = ly + 1, cz = lz + HR::ZH;
-    const AT P0 = sP[R::idx(cx, cy, cz)];
+    const int kb = R::template nb_base<HR::ZH>(lx + 1, ly + 1, lz + HR::ZH);
+    const AT P0 = sP[kb + R::template nb<HR::ZH>(0, 0, 0)];
     // The weight of a link depends on its shell alone, so the link terms are
     // summed per shell, unweighted, in the auxiliary type (a handful of terms
     // of one magnitude class, each a difference rounded relative to itself);
@@ -1186,8 +1194,8 @@ __device__ __forceinline__ void pressure_tile(CDesc& cs, const TileCtx& t, AT* s
 #pragma unroll
     for (int i = 1; i < G::Q; i += 2) {  // pairs (i, i+1) are opposite
         const int s = shell<G>(i);
-        const int km = R::idx(cx - G::c(i, 0), cy - G::c(i, 1), cz - G::c(i, 2));
-        const int kp = R::idx(cx + G::c(i, 0), cy + G::c(i, 1), cz + G::c(i, 2));
+        const int km = kb + R::template nb<HR::ZH>(-G::c(i, 0), -G::c(i, 1), -G::c(i, 2));
+        const int kp = kb + R::template nb<HR::ZH>(G::c(i, 0), G::c(i, 1), G::c(i, 2));
         // the pair's second difference of P
         sks[s] += (sP[km] - P0) + (sP[kp] - P0);
         if (WALL) sgs[s] += sGD[km] + sGD[kp];
@@ -1273,12 +1281,12 @@ __device__ __forceinline__ void velocity_tile(CDesc& cs, const TileCtx& t, CT* s
     const CT ra = cconst<CT>(cs.rho_a, cs.f32.rho_a), dr = cconst<CT>(cs.rho_w - cs.rho_a, cs.f32.drho);
     const CT rho = ra + clamp01(phi) * dr;
     const CT irho = rcp(rho);
-    const int cx = lx + 1, cy = ly + 1, cz = lz + HR::ZH;
+    const int kb = R::template nb_base<HR::ZH>(lx + 1, ly + 1, lz + HR::ZH);
     CT gr[3] = {0, 0, 0};
 #pragma unroll
     for (int i = 1; i < G::Q; i += 2) {
-        const int kp = R::idx(cx + G::c(i, 0), cy + G::c(i, 1), cz + G::c(i, 2));
-        const int km = R::idx(cx - G::c(i, 0), cy - G::c(i, 1), cz - G::c(i, 2));
+        const int kp = kb + R::template nb<HR::ZH>(G::c(i, 0), G::c(i, 1), G::c(i, 2));
+        const int km = kb + R::template nb<HR::ZH>(-G::c(i, 0), -G::c(i, 1), -G::c(i, 2));
         const CT d = (WALL ? (sP[kp] + rho * sGD[kp]) - (sP[km] + rho * sGD[km]) : sP[kp] - sP[km]) * (CT)G::w(i);
 #pragma unroll
         for (int a = 0; a < DIMV; ++a) {
