@@ -5,7 +5,8 @@
 //   k_moments  per node, no halo: gathers h and g (AA pattern) and writes
 //              phi = sum h, u* = sum g c, P* = rho_ref T sum g (the pressure
 //              the populations carry; the stored rest population lacks the
-//              previous P, which is added back) and M2 = sum g c c.
+//              previous P, which is added back) and M2 = sum g c c (in
+//              2-byte storage as 2-byte codes, two to a 32-bit word).
 //   k_pressure 1-halo LDS tile: the pressure formula of Sec. II with K_i of
 //              P* and, in the omega term, u* at x - c_i.  Link terms are
 //              summed per shell in the auxiliary type (FP64 in FP64 storage,
@@ -989,7 +990,9 @@ __device__ __forceinline__ void u_reference(void* u_prev, int64_t N, uint32_t n,
     }
 }
 
-// --- moments: phi, u* = sum g c, P*, M2 (per node; no halo)
+// --- moments: phi, u* = sum g c, P*, M2 (per node; no halo).  NTL: the
+// population loads stream past L2 (non-temporal); odd is the step parity,
+// a constant in every instantiation the kernel calls.
 template <int LS, class S, bool WALL, bool NTL>
 __device__ __forceinline__ void moments_node(CDesc& cs, int x, int y, int z, bool odd)
 {
