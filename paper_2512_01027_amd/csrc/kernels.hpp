@@ -91,7 +91,7 @@ struct CaseDev {
     int32_t fastdiv;
     uint32_t dvh[4], dvl[4];
     int32_t tile_rev;  // 1: the case's tiles are taken in reverse order (a race check, pulbm_set_tile_order)
-    int32_t pad1;
+    int32_t nt_odd_moments;  // 1: k_moments streams its 4- and 8-byte loads on odd steps too
     // Constants of the collision derived once on the host (so no thread
     // divides in FP64): 1 / tau_phi, M / (T W), 48 sigma / W, 1.5 sigma W;
     // and every constant the FP32 kernels use, rounded once to FP32.
@@ -401,13 +401,16 @@ __device__ __forceinline__ bool tile_at_wall(CDesc& cs, int ox, int oy, int oz)
 // written once, and at the sizes that matter the state is far larger than the
 // caches, so accesses can be marked non-temporal.  Which accesses gain from it
 // was measured per storage width (bit 0: loads in k_moments, bit 1: loads in
-// k_collide, bit 2: stores in k_collide): 4- and 8-byte populations stream
-// their loads; 2-byte populations the collide's loads and stores, and
-// k_moments' loads on even steps only (bit 3): on odd steps, shifted by one
-// node in x, a 128-byte line is read half by one tile and half by its x
-// neighbour, and streamed past L2 it is fetched twice.
+// k_collide, bit 2: stores in k_collide, bit 3: loads in k_moments on even
+// steps only): 4- and 8-byte populations stream the collide's loads, 2-byte
+// populations the collide's loads and stores, and both stream k_moments'
+// loads on even steps: on odd steps, shifted by one node in x, a line is
+// read partly by one tile and partly by its x neighbour, and streamed past
+// L2 it is fetched twice.  Wide populations of a small grid stream on odd
+// steps too (CaseDev::nt_odd_moments): the second fetch then hits the
+// last-level cache.
 enum PopAccess { kLoadMoments = 1, kLoadCollide = 2, kStoreCollide = 4, kLoadMomentsEven = 8 };
-constexpr int kNtWide = kLoadMoments | kLoadCollide, kNtHalf = kLoadCollide | kStoreCollide | kLoadMomentsEven;
+constexpr int kNtWide = kLoadMomentsEven | kLoadCollide, kNtHalf = kLoadCollide | kStoreCollide | kLoadMomentsEven;
 template <class S, int A> constexpr bool nt_access() { return ((sizeof(S) >= 4 ? kNtWide : kNtHalf) & A) != 0; }
 
 // Population arriving at the node (byte offset nb) along direction i.
@@ -1085,6 +1088,7 @@ __global__ __launch_bounds__(256) void k_moments(CaseTab cases, const int* hdr, 
     const bool odd = t.step & 1;
     constexpr bool nt_odd = nt_access<S, kLoadMoments>();
     constexpr bool nt_even = nt_odd || nt_access<S, kLoadMomentsEven>();
+    constexpr bool nt_odd_wide = !nt_odd && sizeof(S) >= 4;
     if (tile_at_wall<Mo>(cs, t.ox, t.oy, t.oz)) {
         if (in_block(cs, x, y, z)) {
             // block nodes carry no fluid: phi, u*, P*, M2 = 0
@@ -1109,11 +1113,13 @@ __global__ __launch_bounds__(256) void k_moments(CaseTab cases, const int* hdr, 
             }
             return;
         }
-        if (odd) moments_node<LS, S, true, nt_odd>(cs, x, y, z, true);
-        else moments_node<LS, S, true, nt_even>(cs, x, y, z, false);
+        if (!odd) moments_node<LS, S, true, nt_even>(cs, x, y, z, false);
+        else if (nt_odd_wide && cs.nt_odd_moments) moments_node<LS, S, true, true>(cs, x, y, z, true);
+        else moments_node<LS, S, true, nt_odd>(cs, x, y, z, true);
     } else {
-        if (odd) moments_node<LS, S, false, nt_odd>(cs, x, y, z, true);
-        else moments_node<LS, S, false, nt_even>(cs, x, y, z, false);
+        if (!odd) moments_node<LS, S, false, nt_even>(cs, x, y, z, false);
+        else if (nt_odd_wide && cs.nt_odd_moments) moments_node<LS, S, false, true>(cs, x, y, z, true);
+        else moments_node<LS, S, false, nt_odd>(cs, x, y, z, true);
     }
 }
 
