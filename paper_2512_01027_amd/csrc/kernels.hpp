@@ -402,15 +402,15 @@ __device__ __forceinline__ bool tile_at_wall(CDesc& cs, int ox, int oy, int oz)
 // caches, so accesses can be marked non-temporal.  Which accesses gain from it
 // was measured per storage width (bit 0: loads in k_moments, bit 1: loads in
 // k_collide, bit 2: stores in k_collide, bit 3: loads in k_moments on even
-// steps only): 4- and 8-byte populations stream the collide's loads, 2-byte
-// populations the collide's loads and stores, and both stream k_moments'
-// loads on even steps: on odd steps, shifted by one node in x, a line is
-// read partly by one tile and partly by its x neighbour, and streamed past
-// L2 it is fetched twice.  Wide populations of a small grid stream on odd
-// steps too (CaseDev::nt_odd_moments): the second fetch then hits the
-// last-level cache.
+// steps only): populations of every width stream the collide's loads, the
+// collide's stores on even steps (odd-step stores stay in L2, see
+// collide_tile) and k_moments' loads on even steps: on odd steps, shifted by
+// one node in x, a line is read partly by one tile and partly by its x
+// neighbour, and streamed past L2 it is fetched twice.  Wide populations of
+// a small grid stream on odd steps too (CaseDev::nt_odd_moments): the
+// second fetch then hits the last-level cache.
 enum PopAccess { kLoadMoments = 1, kLoadCollide = 2, kStoreCollide = 4, kLoadMomentsEven = 8 };
-constexpr int kNtWide = kLoadMomentsEven | kLoadCollide, kNtHalf = kLoadCollide | kStoreCollide | kLoadMomentsEven;
+constexpr int kNtWide = kLoadMomentsEven | kLoadCollide | kStoreCollide, kNtHalf = kNtWide;
 template <class S, int A> constexpr bool nt_access() { return ((sizeof(S) >= 4 ? kNtWide : kNtHalf) & A) != 0; }
 
 // Population arriving at the node (byte offset nb) along direction i.
@@ -1391,10 +1391,10 @@ __device__ __forceinline__ void collide_tile(CDesc& cs, const TileCtx& t, typena
     const bool odd = PAR == 0 ? false : (PAR == 2 ? true : (bool)(step_parity(cs, t) & 1));
     const Nav nv = PAR == 2 ? make_nav_inner(cs, (int)sizeof(S))
                             : make_nav(cs, inside ? x : 0, inside ? y : 0, inside ? z : 0, (int)sizeof(S));
-    // 2-byte stores stream past L2 on even steps; on odd steps, shifted by
-    // one node in x, each 128-byte line is written half by this tile and half
-    // by its x neighbour, and kept in L2 the two halves merge (measured: the
-    // odd steps' writes 123 -> 92 B/node)
+    // stores stream past L2 on even steps (FP32 even collide 3% faster); on
+    // odd steps, shifted by one node in x, each line is written partly by
+    // this tile and partly by its x neighbour, and kept in L2 the parts merge
+    // (measured, FP16: the odd steps' writes 123 -> 92 B/node)
     constexpr bool nts = PAR == 0 && nt_access<S, kStoreCollide>();
     const Slots<S> hs = slots<S>(cs.h, cs.N), gs = slots<S>(cs.g, cs.N);
     // own-node loads first
